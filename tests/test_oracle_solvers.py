@@ -1,0 +1,237 @@
+"""Pins of the oracle's solvers and homogenization results."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import homogenization as H
+from oracle import solvers, spectral, tensors
+from paper_1712_05145_amd import microstructure as M
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _two_phase_problem(n, seed, young=(1.0, 10.0), nu=(0.3, 0.3)):
+    phase = M.random_phases(n, 2, seed)
+    lame = M.lame_from_young(young, nu)
+    lam0, mu0 = M.midpoint_reference(lame)
+    return phase, lame, H.make_problem(phase, lam0, mu0, lame=lame)
+
+
+@pytest.mark.parametrize("n,seed", [(4, 1), (5, 2)])
+def test_dense_galerkin_equals_iterative_solutions(n, seed):
+    """The discrete solution is the displacement Galerkin minimiser; BS and CG reach it."""
+    _, _, prob = _two_phase_problem(n, seed)
+    e = np.array([1.0, -0.3, 0.2, 0.4, 0.0, 0.5])
+    ref = solvers.dense_galerkin(prob.C, e_macro=tensors.tensor_from_engineering(e))
+    for scheme in ("basic", "cg"):
+        eps, _, info = H.solve_order0(prob, e, scheme, tol=1e-13)
+        assert info["converged"]
+        assert np.abs(eps - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_dense_galerkin_anisotropic_phases():
+    rng = np.random.default_rng(11)
+    phase = M.random_phases(4, 3, 4)
+    v21 = []
+    for _ in range(3):
+        a = rng.standard_normal((6, 6))
+        c = a @ a.T + 6 * np.eye(6)
+        v21.append([c[i, j] for i in range(6) for j in range(i, 6)])
+    prob = H.make_problem(phase, 3.0, 2.5, voigt21=np.array(v21))
+    e = np.array([0.2, 1.0, 0.0, 0.0, 0.3, 0.0])
+    ref = solvers.dense_galerkin(prob.C, e_macro=tensors.tensor_from_engineering(e))
+    eps, _, info = H.solve_order0(prob, e, "cg", tol=1e-13)
+    assert np.abs(eps - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_dense_galerkin_polarization_rhs():
+    _, _, prob = _two_phase_problem(4, 9)
+    rng = np.random.default_rng(2)
+    p = rng.standard_normal((3, 3, 4, 4, 4))
+    p = 0.5 * (p + np.swapaxes(p, 0, 1))
+    ref = solvers.dense_galerkin(prob.C, p_rhs=p)
+    b = prob.rhs(p)
+    eps, info = solvers.conjugate_gradient(prob, b, 1e-13)
+    assert np.abs(eps - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_reference_equal_to_material_gives_zero_fluctuation():
+    """C == C0: eps = 0 and sigma = C0:E exactly (zero right-hand side)."""
+    phase = np.zeros((6, 6, 6), dtype=np.uint16)
+    prob = H.make_problem(phase, 1.3, 0.8, lame=[[1.3, 0.8]])
+    e = [1.0, 0.5, 0.0, 0.2, 0.0, 0.0]
+    for scheme in ("basic", "cg"):
+        eps, mean, info = H.solve_order0(prob, e, scheme, tol=1e-10)
+        assert info["iters"] == 0 and np.all(eps == 0)
+        sig = np.einsum("ijkl,kl->ij", tensors.isotropic_stiffness(1.3, 0.8), tensors.tensor_from_engineering(e))
+        assert np.allclose(mean, tensors.stress_voigt_from_tensor(sig), rtol=1e-15, atol=1e-15)
+
+
+def test_uniform_material_different_reference():
+    phase = np.zeros((6, 6, 6), dtype=np.uint16)
+    prob = H.make_problem(phase, 2.0, 1.5, lame=[[1.0, 0.5]])
+    eps, mean, info = H.solve_order0(prob, [1, 0, 0, 0, 0, 1], "cg", tol=1e-10)
+    assert info["iters"] == 0 and np.abs(eps).max() == 0
+
+
+def test_garbled_update_diverges_and_fixed_point_converges():
+    """The update printed in Algorithm 1 iterates eps <- A eps and blows up;
+    the fixed point of eq. (5) converges (reading of the Basic Scheme update)."""
+    _, _, prob = _two_phase_problem(6, 3)
+    e = tensors.tensor_from_engineering([1, 0, 0, 0, 0, 0])
+    b = prob.rhs(prob.C.contract_const(e))
+    eps = b.copy()
+    for _ in range(60):
+        eps = eps - prob.green(prob.polarization(eps))         # eps - eta, literally
+    assert tensors.l2norm(eps) > 1e6 * tensors.l2norm(b)
+    x, info = solvers.basic_scheme(prob, b, 1e-10)
+    assert info["converged"] and solvers.true_residual(prob, x, b) < 1e-9
+
+
+def test_basic_scheme_cauchy_equals_residual():
+    """||eps_{n+1} - eps_n|| = ||b - A eps_n||: the stop rule is the equilibrium residual."""
+    _, _, prob = _two_phase_problem(6, 5)
+    b = prob.rhs(prob.C.contract_const(tensors.tensor_from_engineering([0, 1, 0, 0, 0, 0])))
+    eps = b.copy()
+    for _ in range(3):
+        nxt = b + prob.green(prob.polarization(eps))
+        assert abs(tensors.l2norm(nxt - eps) - tensors.l2norm(b - prob.apply_A(eps))) < 1e-13 * tensors.l2norm(b)
+        eps = nxt
+
+
+def test_cg_operator_selfadjoint_in_c0_inner_product():
+    """A is self-adjoint on compatible fields in the C0 inner product, not in L2 when lam0 != 0."""
+    _, _, prob = _two_phase_problem(6, 7)
+    rng = np.random.default_rng(1)
+    u1, u2 = rng.standard_normal((2, 3, 6, 6, 6))
+    a, c = spectral.sym_gradient(u1), spectral.sym_gradient(u2)
+    lhs = prob.ip_c0(prob.apply_A(a), c)
+    rhs = prob.ip_c0(a, prob.apply_A(c))
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+    l2 = tensors.frobenius(prob.apply_A(a), c) - tensors.frobenius(a, prob.apply_A(c))
+    assert abs(l2) > 1e-6 * abs(tensors.frobenius(prob.apply_A(a), c))
+
+
+def test_basic_and_cg_agree_and_c0_independent():
+    phase, lame, prob = _two_phase_problem(8, 12)
+    e = [0.0, 0.0, 1.0, 0.0, 0.0, 0.0]
+    eps1, m1, _ = H.solve_order0(prob, e, "basic", tol=1e-12)
+    eps2, m2, _ = H.solve_order0(prob, e, "cg", tol=1e-12)
+    prob2 = H.make_problem(phase, 8.0, 6.0, lame=lame)
+    eps3, m3, _ = H.solve_order0(prob2, e, "cg", tol=1e-12)
+    scale = np.abs(eps2).max()
+    assert np.abs(eps1 - eps2).max() < 1e-9 * scale
+    assert np.abs(eps3 - eps2).max() < 1e-9 * scale
+    assert np.allclose(m1, m2, rtol=1e-10, atol=1e-12) and np.allclose(m3, m2, rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.parametrize("n,layers", [(8, [0, 0, 1, 1, 1, 1, 0, 0]), (7, [0, 1, 1, 0, 1, 0, 0])])
+def test_laminate_backus(n, layers):
+    """Order 0 on a laminate: C_eff equals the Backus closed form (even layers or odd n)."""
+    phase = M.laminate((n, n, n), layers, axis=2)
+    lame = M.lame_from_young([1.0, 7.0], [0.3, 0.2])
+    lam0, mu0 = M.midpoint_reference(lame)
+    prob = H.make_problem(phase, lam0, mu0, lame=lame)
+    ceff, _, _ = H.effective_stiffness(prob, "cg", tol=1e-13)
+    f1 = np.mean(np.asarray(layers) == 1)
+    ref = H.laminate_backus(lame[:, 0], lame[:, 1], [1 - f1, f1])
+    assert np.abs(ceff - ref).max() < 1e-11 * np.abs(ref).max()
+
+
+def test_effective_tensor_symmetry_cubic_and_bounds():
+    """Centred sphere (config-1 geometry): C_eff symmetric with cubic voxel symmetry;
+    Voigt >= C_eff >= Reuss; Hashin-Shtrikman bulk bounds."""
+    phase, lame = M.centred_sphere(12)
+    lam0, mu0 = M.midpoint_reference(lame)
+    prob = H.make_problem(phase, lam0, mu0, lame=lame)
+    ceff, _, _ = H.effective_stiffness(prob, "cg", tol=1e-12)
+    s = np.abs(ceff).max()
+    assert np.abs(ceff - ceff.T).max() < 1e-9 * s
+    assert abs(ceff[0, 0] - ceff[1, 1]) < 1e-9 * s and abs(ceff[0, 0] - ceff[2, 2]) < 1e-9 * s
+    assert abs(ceff[0, 1] - ceff[0, 2]) < 1e-9 * s and abs(ceff[1, 2] - ceff[0, 1]) < 1e-9 * s
+    assert abs(ceff[3, 3] - ceff[4, 4]) < 1e-9 * s and abs(ceff[3, 3] - ceff[5, 5]) < 1e-9 * s
+    off = ceff.copy()
+    off[:3, :3] = 0
+    np.fill_diagonal(off, 0)
+    assert np.abs(off).max() < 1e-9 * s
+    assert np.linalg.eigvalsh(H.voigt_bound(prob) - ceff).min() > -1e-9 * s
+    assert np.linalg.eigvalsh(ceff - H.reuss_bound(prob)).min() > -1e-9 * s
+    f1 = phase.mean()
+    k = lame[:, 0] + 2 * lame[:, 1] / 3
+    lo, hi = H.hashin_shtrikman_bulk([1 - f1, f1], k, lame[:, 1])
+    kc, ks = H.bulk_energy_measures(ceff)
+    assert kc <= hi * (1 + 1e-9) and ks >= lo * (1 - 1e-9)
+
+
+def test_hashin_golden_neutral_matrix_modulus():
+    """Sec. 4 prints E3 = 453.685 for the neutral matrix; the 2-D plane-stress
+    neutral-coating condition reproduces it."""
+    gold = json.load(open(os.path.join(GOLDEN, "hashin_2d.json")))
+    nu = gold["nu"]
+    k1 = gold["E1_core"] / (2 * (1 - nu))
+    k2 = gold["E2_coating"] / (2 * (1 - nu))
+    mu2 = gold["E2_coating"] / (2 * (1 + nu))
+    f = (gold["r1"] / gold["r2"]) ** 2
+    k3 = k2 + f / (1.0 / (k1 - k2) + (1 - f) / (k2 + mu2))
+    e3 = 2 * k3 * (1 - nu)
+    assert abs(e3 - gold["E3_matrix"]) < 5e-4
+
+
+@pytest.mark.parametrize("n", [32, 64])
+def test_hashin_golden_neutrality_2d(n):
+    """With the printed moduli, the 2-D coated inclusion is neutral: the in-plane
+    bulk modulus of the cell equals that of the matrix up to the voxel error."""
+    gold = json.load(open(os.path.join(GOLDEN, "hashin_2d.json")))
+    nu = gold["nu"]
+    young = np.array([gold["E1_core"], gold["E2_coating"], gold["E3_matrix"]])
+    lame3 = M.lame_from_young(young, [nu] * 3)
+    lam_ps = 2 * lame3[:, 0] * lame3[:, 1] / (lame3[:, 0] + 2 * lame3[:, 1])   # plane-stress lambda
+    lame = np.stack([lam_ps, lame3[:, 1]], axis=1)
+    y = -0.5 + (np.arange(n) + 0.5) / n
+    d = np.sqrt(y[:, None] ** 2 + y[None, :] ** 2)
+    plane = np.full((n, n), 2, dtype=np.uint16)
+    plane[d < gold["r2"]] = 1
+    plane[d < gold["r1"]] = 0
+    phase = plane[:, :, None]
+    lam0, mu0 = M.midpoint_reference(lame)
+    prob = H.make_problem(phase, lam0, mu0, lame=lame)
+    _, mean, info = H.solve_order0(prob, [1, 1, 0, 0, 0, 0], "cg", tol=gold["tol"] * 1e-2)
+    k_eff = (mean[0] + mean[1]) / 4.0
+    k3 = lame[2, 0] + lame[2, 1]
+    assert abs(k_eff / k3 - 1) < 0.02 * 32 / n
+
+
+def test_coated_sphere_3d_neutrality_soft():
+    """3-D analogue: coated sphere with the neutral matrix bulk modulus."""
+    n = 16
+    young = np.array([100.0, 1000.0])
+    lame = M.lame_from_young(young, [0.3, 0.3])
+    k = lame[:, 0] + 2 * lame[:, 1] / 3
+    mu2 = lame[1, 1]
+    f = (0.25 / 0.4) ** 3
+    k3 = k[1] + f / (1 / (k[0] - k[1]) + 3 * (1 - f) / (3 * k[1] + 4 * mu2))
+    e3 = 3 * k3 * (1 - 2 * 0.3)                     # Young's modulus of the neutral matrix
+    lame = np.vstack([lame, M.lame_from_young([e3], [0.3])])
+    phase = M.coated_sphere(n)
+    lam0, mu0 = M.midpoint_reference(lame)
+    prob = H.make_problem(phase, lam0, mu0, lame=lame)
+    _, mean, _ = H.solve_order0(prob, [1, 1, 1, 0, 0, 0], "cg", tol=1e-8)
+    k_eff = (mean[0] + mean[1] + mean[2]) / 9.0
+    assert abs(k_eff / k3 - 1) < 0.015
+
+
+def test_iteration_counts_soft():
+    """Iteration counts are about independent of the grid; CG needs far fewer than BS."""
+    its = {}
+    for n in (8, 16):
+        phase, lame = M.centred_sphere(n, young=(1.0, 100.0))
+        lam0, mu0 = M.midpoint_reference(lame)
+        prob = H.make_problem(phase, lam0, mu0, lame=lame)
+        for scheme in ("basic", "cg"):
+            _, _, info = H.solve_order0(prob, [1, 0, 0, 0, 0, 0], scheme, tol=1e-6)
+            its[(n, scheme)] = info["iters"]
+    assert its[(16, "cg")] < its[(16, "basic")] / 3
+    assert 0.5 < its[(16, "cg")] / its[(8, "cg")] < 2.0
+    assert 0.5 < its[(16, "basic")] / its[(8, "basic")] < 2.0

@@ -1,0 +1,219 @@
+"""Benchmark: FFT-based homogenization on one MI355X.
+
+Workload (default): 256^3 periodic Voronoi polycrystal, 200 seeded grains,
+grain Lame pairs log-uniform in [1, 50], reference medium at the midpoint.
+One step = the six order-0 unit loads (full 6x6 effective stiffness) followed
+by the order-1 problem for the gradient load (grad E)_111 = (grad E)_222 = 1,
+whose right-hand side is built from the six order-0 correctors; CG with FP32
+inner solves and FP64 defect correction to relative residual 1e-8.
+
+Printed value: voxel-iterations per second of the mixed-precision path
+(one voxel-iteration = one voxel x one operator application, FP32 inner and
+FP64 residual applications both counted).  Also reported: the plain FP64 GPU
+path on the same workload at the same tolerance (speedup), p50/p99 step
+latency, the dominant kernel against the HBM roofline (HIP events on the
+plan's stream over the timed steps), and the CPU oracle on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-iters/s at 256^3, mixed vs FP64 to 1e-8 residual; p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic HBM bytes per voxel for one load in one launch of each kernel
+# category (FP32 CG inner iteration; 4-byte words, 2-byte phase ids):
+#   x-pass forward  r, p, phase read; p, half spectrum written   24+24+2+24+24
+#   y-pass / z-pass half spectrum (6 x n/2 complex) read and written  24+24
+#   x-pass inverse  spectrum, p, x, r read; x, r written          24*4+24*2
+ALG_BYTES_F32 = {"xfwd_f32": 98.0, "ypass_f32": 48.0, "zpass_f32": 48.0, "xinv_f32": 144.0}
+# launches of each category per load per inner iteration
+LAUNCHES_PER_ITER = {"xfwd_f32": 1, "ypass_f32": 2, "zpass_f32": 1, "xinv_f32": 1}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def default_grad():
+    g = np.zeros((6, 3))
+    g[0, 0] = 1.0      # dE_11/dY_1
+    g[1, 1] = 1.0      # dE_22/dY_2
+    return g.reshape(1, 18)
+
+
+def cpu_baseline(n_sample, grains, seed):
+    """The FP64 oracle, one operator application on the same generator at n_sample^3."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import homogenization as H
+    from paper_1712_05145_amd import microstructure as M
+    phase, lame = M.voronoi_polycrystal(n_sample, grains, seed)
+    lam0, mu0 = M.midpoint_reference(lame)
+    prob = H.make_problem(phase, lam0, mu0, lame=lame)
+    x = np.random.default_rng(0).standard_normal((3, 3) + phase.shape)
+    x = 0.5 * (x + np.swapaxes(x, 0, 1))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        prob.apply_A(x)
+        dt = time.perf_counter() - t0
+    return {"value": phase.size / dt, "unit": "voxel-iters/s", "cores": 1, "kind": "oracle",
+            "sample": f"one FP64 operator application (FFT, Green operator, inverse FFT) of the oracle on the "
+                      f"{n_sample}^3 Voronoi polycrystal of the same generator, single thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--grains", type=int, default=200)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--scheme", default="cg", choices=["cg", "basic"])
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-n", type=int, default=128)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (the solver is single-GPU; --gpus {args.gpus} is not supported)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1712_05145_amd import ffth
+    from paper_1712_05145_amd import microstructure as M
+
+    if not torch.cuda.is_available():
+        raise SystemExit("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    t = time.perf_counter()
+    phase, lame = M.voronoi_polycrystal(args.n, args.grains, args.seed)
+    lam0, mu0 = M.midpoint_reference(lame)
+    log(f"microstructure {args.n}^3, {args.grains} grains in {time.perf_counter() - t:.1f}s; C0 = ({lam0:.3f}, {mu0:.3f})")
+    nvox = phase.size
+    G = default_grad()
+
+    def make(precision, order, nloads):
+        return ffth.Solver(phase, lam0, mu0, lame=lame, nloads=nloads, order=order, scheme=args.scheme,
+                           precision=precision, tol=args.tol, max_iter=50000, inner_tol=1e-4, max_outer=12,
+                           check_every=8, device=dev)
+
+    s0 = make("mixed", 0, 6)
+    s1 = make("mixed", 1, 1)
+    eps0 = s0.field(6, 6)
+    eps1 = s1.field(6, 1)
+
+    def step(a, b, e0, e1):
+        _, r0 = a.solve_order0(np.eye(6), out=e0)
+        _, r1 = b.solve_order1(e0, G, out=e1)
+        return r0 + r1
+
+    for w in range(args.warmup):
+        step(s0, s1, eps0, eps1)
+        log(f"warmup {w + 1}/{args.warmup} done")
+    ffth.ffth_profile_enable(s0.plan, True)
+    ffth.ffth_profile_enable(s1.plan, True)
+    torch.cuda.synchronize()
+    times, results = [], []
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        ts = time.perf_counter()
+        results.append(step(s0, s1, eps0, eps1))
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - ts)
+        log(f"step {k + 1}/{args.steps}: {times[-1] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    prof0 = ffth.ffth_profile_read(s0.plan)
+    prof1 = ffth.ffth_profile_read(s1.plan)
+    ffth.ffth_profile_enable(s0.plan, False)
+    ffth.ffth_profile_enable(s1.plan, False)
+
+    inner = sum(r["iters"] for rs in results for r in rs)
+    fp64_apps = sum(r["fp64_applications"] for rs in results for r in rs)
+    bad = [r for rs in results for r in rs if r["status"] != 0]
+    if bad:
+        raise SystemExit(f"solve failed: {bad[0]}")
+    value = nvox * (inner + fp64_apps) / elapsed
+    ms_step = elapsed / args.steps * 1e3
+    ceff = np.array([r["mean_stress"] for r in results[-1][:6]]).T
+
+    # roofline of the dominant kernel (FP32 inner-iteration kernels)
+    prof = {k: (prof0[k][0] + prof1[k][0], prof0[k][1] + prof1[k][1]) for k in prof0}
+    inner_units = inner  # load-iterations processed by each FP32 category, per launch kind
+    cat = max(ALG_BYTES_F32, key=lambda c: prof[c][1])
+    launches, tot_ms = prof[cat]
+    units = inner_units * LAUNCHES_PER_ITER[cat]
+    bytes_total = ALG_BYTES_F32[cat] * nvox * units
+    achieved = bytes_total / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
+    kernels = {}
+    for c in prof:
+        n_l, ms = prof[c]
+        entry = {"launches": n_l, "total_ms": round(ms, 3), "avg_ms": round(ms / n_l, 4) if n_l else None}
+        if c in ALG_BYTES_F32 and ms > 0:
+            u = inner_units * LAUNCHES_PER_ITER[c]
+            entry["alg_bytes_per_voxel"] = ALG_BYTES_F32[c]
+            entry["achieved_GBs"] = round(ALG_BYTES_F32[c] * nvox * u / (ms * 1e-3) / 1e9, 1)
+        kernels[c] = entry
+    roofline = {"bound": "hbm", "kernel": cat, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "alg_bytes_per_voxel": ALG_BYTES_F32[cat], "units_per_launch": round(units / max(launches, 1), 3),
+                "avg_launch_ms": round(tot_ms / max(launches, 1), 4)}
+
+    line = {
+        "metric": METRIC, "value": round(value, 1), "unit": "voxel-iters/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 2), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": f"voronoi{args.n}-order0x6+order1", "grid": [args.n] * 3, "grains": args.grains,
+                   "seed": args.seed, "scheme": args.scheme, "precision": "mixed", "tol": args.tol,
+                   "loads_order0": 6, "loads_order1": 1, "parallelism": "single-gpu"},
+        "voxel_iters": {"fp32_inner": int(inner * nvox / args.steps), "fp64": int(fp64_apps * nvox / args.steps)},
+        "iters_per_step": {"fp32_inner": inner // args.steps, "fp64_applications": fp64_apps // args.steps},
+        "latency_ms": {"p50": round(float(np.percentile(times, 50)) * 1e3, 2),
+                       "p99": round(float(np.percentile(times, 99)) * 1e3, 2), "over": "timed steps"},
+        "roofline": roofline,
+        "kernels": kernels,
+    }
+    del s0, s1
+    torch.cuda.empty_cache()
+
+    if not args.no_fp64:
+        f0 = make("fp64", 0, 6)
+        f1 = make("fp64", 1, 1)
+        e0 = f0.field(6, 6)
+        e1 = f1.field(6, 1)
+        torch.cuda.synchronize()
+        tf = time.perf_counter()
+        rf = step(f0, f1, e0, e1)
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - tf
+        it64 = sum(r["iters"] for r in rf)
+        c64 = np.array([r["mean_stress"] for r in rf[:6]]).T
+        diff = np.abs(ceff - c64) / np.sqrt(np.outer(np.diag(c64), np.diag(c64)))
+        apps64 = sum(r["fp64_applications"] for r in rf)
+        line["fp64_path"] = {"ms_per_step": round(t64 * 1e3, 2), "iters_per_step": it64,
+                             "voxel_iters_per_s": round(nvox * apps64 / t64, 1),
+                             "speedup_mixed_vs_fp64": round(t64 * 1e3 / ms_step, 3),
+                             "ceff_max_scaled_diff": float(diff.max()),
+                             "residuals": [r["residual"] for r in rf]}
+        log(f"fp64 step {t64 * 1e3:.1f} ms, C_eff diff {diff.max():.2e}")
+        del f0, f1, e0, e1
+        torch.cuda.empty_cache()
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_n, args.grains, args.seed)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

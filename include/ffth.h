@@ -1,0 +1,194 @@
+/*
+ * ffth.h - C-ABI of libffth, an MI355X (gfx950) implementation of FFT-based
+ * numerical homogenization of orders 0 and 1:
+ *
+ *   F. Dietrich, D. Merkert, B. Simeon, "Derivation of higher-order terms in
+ *   FFT-based numerical homogenization", arXiv:1712.05145.
+ *
+ * The library solves, on a periodic voxel grid of the unit cell [-1/2,1/2)^3
+ * (Sec. 2), the linear system of eq. (6)
+ *
+ *      (Id + Gamma0 * (C - C0)) : eps = -Gamma0 * P_rhs
+ *
+ * with P_rhs = C:E for the classical cell problem ("order 0", the paper's
+ * alpha = 1, Sec. 3 Definition) and P_rhs = p_2 + theta_2 for the
+ * strain-gradient problem ("order 1", alpha = 2, built from the six order-0
+ * correctors, Sec. 3 and eq. (12)).  Two iterations are offered: the Basic
+ * Scheme (fixed point of eq. (5)) and conjugate gradients on eq. (6)
+ * (Algorithm 1, CG version), in FP64, FP32, or FP32 with an FP64
+ * defect-correction outer loop.
+ *
+ * Conventions (fixed by this library where the paper is silent):
+ *   grid      n[3] voxels, C order, grid axis d carries x_{d+1}; voxel centres
+ *             -1/2 + (j + 1/2)/n_d; every n_d even and in the supported set
+ *             (ffth_size_supported).
+ *   fields    strain-like fields are 6 tensor components per voxel in the
+ *             order (11, 22, 33, 23, 13, 12), stored component-major:
+ *             field[c * N + voxel], N = n0*n1*n2.
+ *   E         macroscopic strain as an engineering Voigt 6-vector
+ *             (e11, e22, e33, 2e23, 2e13, 2e12).
+ *   G         strain-gradient load G[J*3 + j] = dE_kl/dY_j for the Voigt
+ *             pair J = (k,l), tensor components.
+ *   stiffness per phase, either (lambda, mu) or 21 upper-triangular Voigt
+ *             coefficients C_11..C_16, C_22..C_26, ..., C_66 (engineering
+ *             shear).
+ *   DFT       forward exp(-2 pi i k.j/n), xi = 2 pi k; every mode with an index
+ *             k_d = -n_d/2 is zero in the output of every spectral operator;
+ *             the zero frequency is zero in the Green operator output.
+ *   residual  ||b - A eps||_L2 / ||b||_L2 (equal to the Cauchy criterion stated
+ *             after Algorithm 1 for the Basic Scheme).
+ *
+ * Memory ownership: every device buffer (phase ids, correctors, outputs and
+ * the workspace) is allocated and freed by the caller.  The library never
+ * allocates device memory; a plan owns host state only.  Host arrays passed
+ * in are copied before the call returns.
+ *
+ * Errors: every call returns an ffth_status; arguments are validated before
+ * any device work is queued.  On FFTH_ERR_NOT_CONVERGED / FFTH_ERR_DIVERGED the
+ * output holds the last iterate and the result records are filled.  A plan is
+ * not thread-safe: use one plan per host thread and stream.
+ */
+#ifndef FFTH_H
+#define FFTH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FFTH_OK = 0,
+  FFTH_ERR_INVALID = 1,        /* bad argument (sizes, reference medium, pointers)  */
+  FFTH_ERR_OOM = 2,            /* workspace smaller than ffth_workspace_bytes()     */
+  FFTH_ERR_NOT_CONVERGED = 3,  /* max_iter reached                                  */
+  FFTH_ERR_DIVERGED = 4,       /* residual not finite or grew by more than 1e6      */
+  FFTH_ERR_DEVICE = 5,         /* HIP runtime error or no usable device             */
+  FFTH_ERR_BUSY = 6,           /* request still running (serving)                   */
+  FFTH_ERR_CANCELLED = 7       /* request cancelled (serving)                       */
+} ffth_status;
+
+typedef enum { FFTH_BASIC = 0, FFTH_CG = 1 } ffth_scheme;
+typedef enum { FFTH_FP64 = 0, FFTH_FP32 = 1, FFTH_MIXED = 2 } ffth_precision;
+
+/* The cell problem of Sec. 2: stiffness field C(x) = table[phase[x]] with
+ * major and minor symmetries, and the isotropic reference medium C0 with
+ * Lame parameters (lambda0, mu0).  mu0 != 0 and lambda0 + 2 mu0 != 0 are
+ * required (the Green operator formula below eq. (5) divides by both); the
+ * CG scheme also needs mu0 > 0 and 3 lambda0 + 2 mu0 > 0 (positive C0). */
+typedef struct {
+  int32_t n[3];               /* voxels per axis                                       */
+  int32_t nphases;            /* entries in the phase table (1..65535)                 */
+  const uint16_t *phase;      /* DEVICE, n0*n1*n2 ids < nphases, caller-owned; must stay
+                                 valid for the lifetime of the plan                    */
+  const double *lame;         /* HOST, nphases x 2 (lambda, mu), or NULL               */
+  const double *stiffness;    /* HOST, nphases x 21 Voigt upper triangle, or NULL;
+                                 exactly one of lame / stiffness is non-NULL           */
+  double lambda0, mu0;        /* reference medium C0                                   */
+} ffth_problem;
+
+typedef struct {
+  int32_t scheme;             /* ffth_scheme                                           */
+  int32_t precision;          /* ffth_precision                                        */
+  double tol;                 /* relative equilibrium residual to reach (e.g. 1e-8)    */
+  int32_t max_iter;           /* iterations (FP64/FP32) or total inner iterations      */
+  double inner_tol;           /* MIXED: relative tolerance of each FP32 inner solve    */
+  int32_t max_outer;          /* MIXED: FP64 defect-correction sweeps                  */
+  int32_t check_every;        /* iterations between host reads of the convergence flags */
+} ffth_opts;
+
+typedef struct {
+  int32_t status;             /* ffth_status of this load case                         */
+  int32_t iters;              /* operator applications in the iteration (FP32 inner
+                                 ones for MIXED)                                       */
+  int32_t outer_iters;        /* MIXED: FP64 residual sweeps; else 0                    */
+  int32_t fp64_applications;  /* FP64 operator applications (incl. the right-hand side) */
+  double residual;            /* final relative residual (FP64 true residual for MIXED) */
+  double mean_stress[6];      /* order 0: Voigt <C:(E+eps)>; order 1: <C:eps + p_2>     */
+  double g_mean[3];           /* order 1: the dropped mean <g> of the body force        */
+  double seconds;             /* wall time of the call this load belonged to            */
+} ffth_result;
+
+typedef struct ffth_plan ffth_plan;
+
+/* Default options: CG, MIXED, tol 1e-8, max_iter 20000, inner_tol 1e-4,
+ * max_outer 12, check_every 8. */
+void ffth_default_opts(ffth_opts *o);
+
+/* 1 if n (one axis length) is supported by the compiled FFT kernels. */
+int32_t ffth_size_supported(int32_t n);
+
+/* Bytes of caller-owned device workspace needed by a plan for grids of size
+ * n[3], a phase table of `nphases` entries, up to `nloads` simultaneous load
+ * cases, order 0 or 1 and the given options.  Returns 0 for invalid
+ * arguments. */
+size_t ffth_workspace_bytes(const int32_t n[3], int32_t nphases, int32_t nloads, int32_t order,
+                            const ffth_opts *o);
+
+/* Create a plan for problem p (Sec. 2: stiffness field, reference medium).
+ * workspace: DEVICE, at least ffth_workspace_bytes(p->n, nloads, order, o)
+ * bytes, 256-byte aligned, caller-owned, must outlive the plan.
+ * hip_stream: hipStream_t on which all work is queued (NULL = default). */
+ffth_status ffth_plan_create(ffth_plan **out, const ffth_problem *p, const ffth_opts *o,
+                             int32_t nloads, int32_t order, void *workspace, size_t bytes,
+                             void *hip_stream);
+
+ffth_status ffth_plan_destroy(ffth_plan *plan);
+
+/* Order 0, the classical cell problem (Sec. 2 eqs. (1)-(6); Algorithm 1 with
+ * the initialization eps_0 = -Gamma0 * (C:E)).
+ *   E:   HOST [nloads][6] engineering Voigt macro strains.
+ *   eps: DEVICE FP64 out [nloads][6][N] strain fluctuation (tensor components).
+ *   res: HOST out [nloads]. */
+ffth_status ffth_solve_order0(ffth_plan *plan, int32_t nloads, const double *E, double *eps,
+                              ffth_result *res);
+
+/* Order 1, the strain-gradient problem (Sec. 3, alpha = 2): right-hand side
+ * p_2 = C : sym(X_1 . grad E) and body force g_2 = div_Y[C : (e_y(X_1:E) + E)]
+ * built from the six order-0 correctors, turned into the polarization theta_2
+ * of eq. (12) (mean of g dropped and reported), then the same iteration with
+ * eps_0 = -Gamma0 * (p_2 + theta_2).
+ *   eps0_six: DEVICE FP64 [6][6][N] order-0 strain fluctuations for the unit
+ *             engineering loads e_1..e_6 (as returned by ffth_solve_order0).
+ *   G:        HOST [nloads][18] strain gradients.
+ *   eps:      DEVICE FP64 out [nloads][6][N]. */
+ffth_status ffth_solve_order1(ffth_plan *plan, const double *eps0_six, int32_t nloads,
+                              const double *G, double *eps, ffth_result *res);
+
+/* Green operator application eta = -Gamma0 * tau (eq. (5) and the formula
+ * below it; the Fourier-space steps of Algorithm 1), one 6-component field.
+ *   tau, eta: DEVICE FP64 [6][N] (may alias).  precision: FFTH_FP64 or
+ *   FFTH_FP32 (input rounded to FP32, output widened back). */
+ffth_status ffth_green_apply(ffth_plan *plan, const double *tau, double *eta, int32_t precision);
+
+/* Zero-mean periodic displacement u with sym grad u = eps (inverse of eq. (1),
+ * used for the corrector X_1 of the ansatz u_1 = X_1 : E in Sec. 3).
+ *   eps: DEVICE FP64 [6][N]; u: DEVICE FP64 out [3][N]. */
+ffth_status ffth_displacement(ffth_plan *plan, const double *eps, double *u);
+
+/* Order-1 right-hand side polarization P = p_2 + theta_2 (Sec. 3, eq. (12))
+ * for one gradient load.  eps0_six as in ffth_solve_order1; G: HOST [18];
+ * P: DEVICE FP64 out [6][N]; g_mean: HOST out [3] (may be NULL). */
+ffth_status ffth_order1_rhs(ffth_plan *plan, const double *eps0_six, const double *G, double *P,
+                            double *g_mean);
+
+/* Kernel timing (diagnostics).  When enabled, every kernel launch of the plan
+ * is bracketed by HIP events recorded on the plan's stream; the totals per
+ * kernel category (0 .. 9: x-pass forward / y-pass / z-pass / x-pass inverse
+ * in FP32, the same four in FP64, finalize, pointwise) accumulate until the
+ * next ffth_profile_enable call, which also resets them. */
+ffth_status ffth_profile_enable(ffth_plan *plan, int32_t on);
+ffth_status ffth_profile_read(ffth_plan *plan, int32_t category, int64_t *launches, double *ms);
+const char *ffth_profile_name(int32_t category);
+
+const char *ffth_status_string(ffth_status s);
+
+/* Last HIP error text recorded by the library on this thread ("" if none). */
+const char *ffth_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FFTH_H */

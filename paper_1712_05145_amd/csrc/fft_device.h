@@ -1,0 +1,266 @@
+// Device building blocks for the 3-D real FFTs of the homogenization solver:
+// complex arithmetic, radix-2/3/4/5/8/16 butterflies in registers, a
+// mixed-radix Stockham FFT over batches of sequences resident in LDS, and
+// wave/block reductions.  gfx950 (CDNA4): 64-wide wavefronts.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ffth {
+
+template <typename T> struct C2 { T x, y; };
+
+template <typename T> __device__ __forceinline__ C2<T> mk(T a, T b) { return C2<T>{a, b}; }
+template <typename T> __device__ __forceinline__ C2<T> operator+(C2<T> a, C2<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T> __device__ __forceinline__ C2<T> operator-(C2<T> a, C2<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T> __device__ __forceinline__ C2<T> operator*(C2<T> a, T s) { return {a.x * s, a.y * s}; }
+template <typename T> __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T> __device__ __forceinline__ C2<T> conj(C2<T> a) { return {a.x, -a.y}; }
+// multiply by +i (DIR>0) or -i (DIR<0)
+template <int DIR, typename T> __device__ __forceinline__ C2<T> mul_i(C2<T> a) {
+  return DIR > 0 ? C2<T>{-a.y, a.x} : C2<T>{a.y, -a.x};
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time factorisation of a transform length into radices 16,8,4,2,3,5.
+// ---------------------------------------------------------------------------
+constexpr int fac_count(int n) {
+  int c = 0;
+  const int rs[6] = {16, 8, 4, 2, 3, 5};
+  for (int i = 0; i < 6; ++i)
+    while (n > 1 && n % rs[i] == 0) { n /= rs[i]; ++c; }
+  return n == 1 ? c : -1;
+}
+constexpr int fac_radix(int n, int s) {
+  const int rs[6] = {16, 8, 4, 2, 3, 5};
+  int c = 0;
+  for (int i = 0; i < 6; ++i)
+    while (n > 1 && n % rs[i] == 0) {
+      if (c == s) return rs[i];
+      n /= rs[i];
+      ++c;
+    }
+  return 1;
+}
+constexpr int fac_prefix(int n, int s) {  // product of radices before stage s
+  int p = 1;
+  for (int i = 0; i < s; ++i) p *= fac_radix(n, i);
+  return p;
+}
+
+// ---------------------------------------------------------------------------
+// Small DFTs in registers.  DIR = -1 forward (exp(-2 pi i/R)), +1 inverse.
+// ---------------------------------------------------------------------------
+#define FFTH_C16_1 0.92387953251128675613
+#define FFTH_S16_1 0.38268343236508977173
+#define FFTH_SQRT_HALF 0.70710678118654752440
+#define FFTH_S3 0.86602540378443864676
+#define FFTH_C5_1 0.30901699437494742410
+#define FFTH_S5_1 0.95105651629515357212
+#define FFTH_C5_2 (-0.80901699437494742410)
+#define FFTH_S5_2 0.58778525229247312917
+
+template <int DIR, typename T> __device__ __forceinline__ void dft2(C2<T>& a, C2<T>& b) {
+  C2<T> t = a;
+  a = t + b;
+  b = t - b;
+}
+
+template <int DIR, typename T> __device__ __forceinline__ void dft4(C2<T>& a0, C2<T>& a1, C2<T>& a2, C2<T>& a3) {
+  C2<T> t0 = a0 + a2, t1 = a0 - a2, t2 = a1 + a3, t3 = mul_i<DIR>(a1 - a3);
+  a0 = t0 + t2;
+  a2 = t0 - t2;
+  a1 = t1 + t3;
+  a3 = t1 - t3;
+}
+
+template <int DIR, typename T> __device__ __forceinline__ void dft3(C2<T>& a0, C2<T>& a1, C2<T>& a2) {
+  // X1 = a0 + w a1 + w^2 a2, w = exp(DIR 2 pi i/3) = -1/2 + DIR i sqrt(3)/2
+  C2<T> s = a1 + a2, d = a1 - a2;
+  C2<T> m = a0 - s * T(0.5);
+  C2<T> r = mul_i<DIR>(d) * T(FFTH_S3);
+  a0 = a0 + s;
+  a1 = m + r;
+  a2 = m - r;
+}
+
+template <int DIR, typename T>
+__device__ __forceinline__ void dft5(C2<T>& a0, C2<T>& a1, C2<T>& a2, C2<T>& a3, C2<T>& a4) {
+  C2<T> s1 = a1 + a4, d1 = a1 - a4, s2 = a2 + a3, d2 = a2 - a3;
+  C2<T> m1 = a0 + s1 * T(FFTH_C5_1) + s2 * T(FFTH_C5_2);
+  C2<T> m2 = a0 + s1 * T(FFTH_C5_2) + s2 * T(FFTH_C5_1);
+  C2<T> r1 = mul_i<DIR>(d1 * T(FFTH_S5_1) + d2 * T(FFTH_S5_2));
+  C2<T> r2 = mul_i<DIR>(d1 * T(FFTH_S5_2) - d2 * T(FFTH_S5_1));
+  a0 = a0 + s1 + s2;
+  a1 = m1 + r1;
+  a4 = m1 - r1;
+  a2 = m2 + r2;
+  a3 = m2 - r2;
+}
+
+// exp(DIR * 2 pi i * m / 16) for m in [0, 16)
+template <int DIR, typename T> __device__ __forceinline__ C2<T> w16(int m) {
+  const T c[16] = {T(1), T(FFTH_C16_1), T(FFTH_SQRT_HALF), T(FFTH_S16_1), T(0), T(-FFTH_S16_1),
+                   T(-FFTH_SQRT_HALF), T(-FFTH_C16_1), T(-1), T(-FFTH_C16_1), T(-FFTH_SQRT_HALF),
+                   T(-FFTH_S16_1), T(0), T(FFTH_S16_1), T(FFTH_SQRT_HALF), T(FFTH_C16_1)};
+  const T s = c[(m + 12) & 15];  // sin(2 pi m/16) = cos(2 pi (m - 4)/16)
+  return C2<T>{c[m & 15], DIR > 0 ? s : -s};
+}
+
+template <int R, int DIR, typename T> __device__ __forceinline__ void dft(C2<T>* a) {
+  if constexpr (R == 2) {
+    dft2<DIR>(a[0], a[1]);
+  } else if constexpr (R == 3) {
+    dft3<DIR>(a[0], a[1], a[2]);
+  } else if constexpr (R == 4) {
+    dft4<DIR>(a[0], a[1], a[2], a[3]);
+  } else if constexpr (R == 5) {
+    dft5<DIR>(a[0], a[1], a[2], a[3], a[4]);
+  } else if constexpr (R == 8) {
+    // 8 = 2 x 4: Y_s = DFT4(a[2m+s]); X[k2 + 4 k1] = sum_s w2^{k1 s} w8^{k2 s} Y_s[k2]
+    dft4<DIR>(a[0], a[2], a[4], a[6]);
+    dft4<DIR>(a[1], a[3], a[5], a[7]);
+    C2<T> y1[4] = {a[1], cmul(a[3], w16<DIR, T>(2)), cmul(a[5], w16<DIR, T>(4)), cmul(a[7], w16<DIR, T>(6))};
+    C2<T> y0[4] = {a[0], a[2], a[4], a[6]};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      a[k] = y0[k] + y1[k];
+      a[k + 4] = y0[k] - y1[k];
+    }
+  } else if constexpr (R == 16) {
+    // 16 = 4 x 4: Y_s = DFT4(a[4m+s]); twiddle w16^{k2 s}; X[k2 + 4 k1] = DFT4_s
+    C2<T> y[4][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      C2<T> b0 = a[s], b1 = a[s + 4], b2 = a[s + 8], b3 = a[s + 12];
+      dft4<DIR>(b0, b1, b2, b3);
+      y[s][0] = b0;
+      y[s][1] = s ? cmul(b1, w16<DIR, T>(s)) : b1;
+      y[s][2] = s ? cmul(b2, w16<DIR, T>(2 * s)) : b2;
+      y[s][3] = s ? cmul(b3, w16<DIR, T>(3 * s)) : b3;
+    }
+#pragma unroll
+    for (int k2 = 0; k2 < 4; ++k2) {
+      C2<T> b0 = y[0][k2], b1 = y[1][k2], b2 = y[2][k2], b3 = y[3][k2];
+      dft4<DIR>(b0, b1, b2, b3);
+      a[k2] = b0;
+      a[k2 + 4] = b1;
+      a[k2 + 8] = b2;
+      a[k2 + 12] = b3;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Twiddle table w[m] = exp(-2 pi i m / N), m in [0, N), built in LDS from
+// sincospi in FP64 (then rounded to T).
+// ---------------------------------------------------------------------------
+template <typename T, int N, int NT> __device__ __forceinline__ void build_twiddles(C2<T>* tw) {
+  for (int m = threadIdx.x; m < N; m += NT) {
+    double s, c;
+    sincospi(-2.0 * (double)m / (double)N, &s, &c);
+    tw[m] = C2<T>{(T)c, (T)s};
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batched in-place Stockham FFT in LDS.
+//   NFFT sequences of length N; element e of sequence f is at
+//   buf[f*FS + PAD(e*ES)] where PAD inserts one slot every 16 when PADDED.
+//   FFAST: consecutive threads take consecutive sequences (strided layouts);
+//   otherwise consecutive butterflies of one sequence (contiguous layouts).
+// Every stage: all reads to registers, barrier, all writes, barrier.
+// ---------------------------------------------------------------------------
+template <bool PADDED> __device__ __forceinline__ int padx(int e) { return PADDED ? e + (e >> 4) : e; }
+
+template <typename T, int N, int S, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR>
+__device__ __forceinline__ void fft_stage(C2<T>* buf, const C2<T>* tw) {
+  constexpr int R = fac_radix(N, S);
+  constexpr int NS = fac_prefix(N, S);
+  constexpr int NB = N / R;
+  constexpr int ITEMS = NFFT * NB;
+  constexpr int K = (ITEMS + NT - 1) / NT;
+  C2<T> v[K][R];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int it = threadIdx.x + k * NT;
+    if ((ITEMS % NT == 0) || it < ITEMS) {
+      const int f = FFAST ? it % NFFT : it / NB;
+      const int j = FFAST ? it / NFFT : it % NB;
+      const C2<T>* src = buf + f * FS;
+      const int kk = j % NS;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        C2<T> a = src[padx<PADDED>((j + r * NB) * ES)];
+        if (NS > 1 && r > 0) {
+          C2<T> w = tw[r * kk * (N / (NS * R))];
+          if (DIR > 0) w.y = -w.y;
+          a = cmul(a, w);
+        }
+        v[k][r] = a;
+      }
+      dft<R, DIR>(v[k]);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const int it = threadIdx.x + k * NT;
+    if ((ITEMS % NT == 0) || it < ITEMS) {
+      const int f = FFAST ? it % NFFT : it / NB;
+      const int j = FFAST ? it / NFFT : it % NB;
+      C2<T>* dst = buf + f * FS;
+      const int base = (j / NS) * NS * R + (j % NS);
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[padx<PADDED>((base + r * NS) * ES)] = v[k][r];
+    }
+  }
+  __syncthreads();
+}
+
+template <typename T, int N, int S, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR>
+__device__ __forceinline__ void fft_stages(C2<T>* buf, const C2<T>* tw) {
+  if constexpr (S < fac_count(N)) {
+    fft_stage<T, N, S, NFFT, NT, ES, FS, FFAST, PADDED, DIR>(buf, tw);
+    fft_stages<T, N, S + 1, NFFT, NT, ES, FS, FFAST, PADDED, DIR>(buf, tw);
+  }
+}
+
+// Caller must __syncthreads() before (data written) - the stages end with a barrier.
+template <typename T, int N, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR>
+__device__ __forceinline__ void lds_fft(C2<T>* buf, const C2<T>* tw) {
+  static_assert(fac_count(N) > 0, "unsupported FFT length");
+  fft_stages<T, N, 0, NFFT, NT, ES, FS, FFAST, PADDED, DIR>(buf, tw);
+}
+
+// ---------------------------------------------------------------------------
+// Reductions: NR double sums per block, fixed order (deterministic).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+template <int NR, int NT>
+__device__ __forceinline__ void block_sums(double (&v)[NR], double* out /* NR doubles */) {
+  __shared__ double red[NT / 64][NR];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();  // red may still be read by a previous call
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    double s = wave_sum(v[r]);
+    if (lane == 0) red[w][r] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < NR) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += red[i][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+}  // namespace ffth

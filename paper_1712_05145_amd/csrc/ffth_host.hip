@@ -1,0 +1,979 @@
+// libffth host driver: plans, workspace layout, the Basic Scheme / CG /
+// mixed-precision solve loops, the order-1 right-hand side, and the C-ABI
+// declared in include/ffth.h.
+//
+// Every step of the iteration runs in the HIP kernels of this library; the
+// host only queues launches, uploads small descriptor/state structs and reads
+// the per-load convergence flags every `check_every` iterations.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ffth.h"
+#include "ffth_launch.h"
+#include "ffth_types.h"
+
+using namespace ffth;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+constexpr int NRED_ = NRED;
+constexpr int MS_BLOCKS_MAX = 1024;   // blocks of the pointwise reduction kernels
+constexpr int NT = 256;              // threads per block of the pointwise kernels
+constexpr size_t ALIGN = 256;
+
+size_t al(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool hip_ok(hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+  return false;
+}
+#define HIPCHK(call)                                  \
+  do {                                                \
+    if (!hip_ok((call), #call)) return FFTH_ERR_DEVICE; \
+  } while (0)
+
+// Workspace regions (byte offsets).  Computed identically for sizing and
+// for carving a caller's buffer.
+struct Layout {
+  size_t mat64, mat32, desc, state, part, spec, f32, f64, P, X1, g, misc, total;
+  size_t spec_stride, f32_stride, f64_stride, part_stride;
+  int nf32, nf64;
+  int ndesc, nstate, nblk;
+};
+
+int x_blocks(int n0, int n1, int n2, bool dbl) {
+  const long rows = (long)n0 * n1;
+  const int r = dbl ? Launch<double>::x_rows(n2) : Launch<float>::x_rows(n2);
+  return r > 0 ? (int)((rows + r - 1) / r) : 0;
+}
+
+int ms_blocks(long nvox) { return (int)std::min<long>(MS_BLOCKS_MAX, (nvox + NT - 1) / NT); }
+
+Layout make_layout(const int n[3], int nph, int nloads, int order, const ffth_opts& o) {
+  Layout L{};
+  const long nvox = (long)n[0] * n[1] * n[2];
+  const int prec = o.precision, scheme = o.scheme;
+  L.ndesc = 7 * nloads + 8;
+  L.nstate = 3 * nloads + 1;
+  L.nblk = std::max({x_blocks(n[0], n[1], n[2], true), x_blocks(n[0], n[1], n[2], false), ms_blocks(nvox)});
+  // per-load FP32 / FP64 field counts
+  if (prec == FFTH_FP32) L.nf32 = scheme == FFTH_CG ? 3 : 1;
+  if (prec == FFTH_MIXED) L.nf32 = scheme == FFTH_CG ? 3 : 2;
+  if (prec == FFTH_FP64) L.nf64 = scheme == FFTH_CG ? 2 : 0;
+  if (prec == FFTH_MIXED) L.nf64 = 1;   // FP64 residual before its compatible projection
+  L.spec_stride = al((size_t)nvox * 6 * sizeof(double));     // 6 x (nvox/2) complex FP64
+  L.f32_stride = al((size_t)nvox * 6 * sizeof(float));
+  L.f64_stride = al((size_t)nvox * 6 * sizeof(double));
+  L.part_stride = al((size_t)L.nblk * NRED_ * sizeof(double));
+  size_t off = 0;
+  L.mat64 = off; off += al((size_t)nph * 72 * sizeof(double));
+  L.mat32 = off; off += al((size_t)nph * 72 * sizeof(float));
+  L.desc = off; off += al((size_t)L.ndesc * sizeof(Desc));
+  L.state = off; off += al((size_t)L.nstate * sizeof(SolverState));
+  L.misc = off; off += ALIGN;
+  L.part = off; off += (size_t)(2 * nloads + 2) * L.part_stride;
+  L.spec = off; off += (size_t)nloads * L.spec_stride;
+  L.f32 = off; off += (size_t)nloads * L.nf32 * L.f32_stride;
+  L.f64 = off; off += (size_t)nloads * L.nf64 * L.f64_stride;
+  L.P = off;
+  if (order == 1) off += (size_t)nloads * L.f64_stride;
+  L.X1 = off;
+  if (order == 1) off += al((size_t)nvox * 18 * sizeof(double));
+  L.g = off;
+  if (order == 1) off += (size_t)nloads * al((size_t)nvox * 3 * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+bool opts_valid(const ffth_opts& o) {
+  if (o.scheme != FFTH_BASIC && o.scheme != FFTH_CG) return false;
+  if (o.precision < FFTH_FP64 || o.precision > FFTH_MIXED) return false;
+  if (!(o.tol > 0.0) || o.max_iter < 1 || o.check_every < 1) return false;
+  if (o.precision == FFTH_MIXED && (!(o.inner_tol > 0.0) || o.inner_tol >= 1.0 || o.max_outer < 1)) return false;
+  return true;
+}
+
+void voigt21_to_m(const double* v21, double m[36]) {
+  double c[6][6];
+  int k = 0;
+  for (int a = 0; a < 6; ++a)
+    for (int b = a; b < 6; ++b) c[a][b] = c[b][a] = v21[k++];
+  // sigma_a = sum_b C_ab * eps_eng_b, eps_eng_b = eps_b (b < 3) or 2 eps_b (shear)
+  for (int a = 0; a < 6; ++a)
+    for (int b = 0; b < 6; ++b) m[a * 6 + b] = c[a][b] * (b < 3 ? 1.0 : 2.0);
+}
+
+void iso_to_m(double lam, double mu, double m[36]) {
+  for (int i = 0; i < 36; ++i) m[i] = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    for (int b = 0; b < 3; ++b) m[a * 6 + b] = lam;
+    m[a * 6 + a] += 2.0 * mu;
+  }
+  for (int a = 3; a < 6; ++a) m[a * 6 + a] = 2.0 * mu;
+}
+
+}  // namespace
+
+struct ffth_plan {
+  int n[3];
+  long nvox;
+  int h;
+  long rows;
+  int nph;
+  bool iso;
+  double lam0, mu0;
+  const uint16_t* phase;
+  hipStream_t stream;
+  int nloads;
+  int order;
+  ffth_opts opts;
+  char* ws;
+  Layout L;
+  double* mat64;
+  float* mat32;
+  Desc* d_desc;
+  SolverState* d_state;
+  SolverState* h_state;   // pinned host mirror (read-back)
+  int nx64, nx32;         // x-pass blocks per precision
+  std::vector<Desc> h_desc;
+  // kernel timing (diagnostics): events bracket every launch when enabled
+  bool prof = false;
+  struct Rec { int cat; hipEvent_t a, b; };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  double prof_ms[16] = {0};
+  long prof_n[16] = {0};
+};
+
+namespace {
+
+double* part_ptr(ffth_plan* P, int slot) { return (double*)(P->ws + P->L.part + (size_t)slot * P->L.part_stride); }
+void* spec_ptr(ffth_plan* P, int l) { return P->ws + P->L.spec + (size_t)l * P->L.spec_stride; }
+float* f32_ptr(ffth_plan* P, int l, int k) {
+  return (float*)(P->ws + P->L.f32 + ((size_t)l * P->L.nf32 + k) * P->L.f32_stride);
+}
+double* f64_ptr(ffth_plan* P, int l, int k) {
+  return (double*)(P->ws + P->L.f64 + ((size_t)l * P->L.nf64 + k) * P->L.f64_stride);
+}
+double* Pfield(ffth_plan* P, int l) { return (double*)(P->ws + P->L.P + (size_t)l * P->L.f64_stride); }
+double* X1field(ffth_plan* P) { return (double*)(P->ws + P->L.X1); }
+double* gfield(ffth_plan* P, int l) {
+  return (double*)(P->ws + P->L.g + (size_t)l * al((size_t)P->nvox * 3 * sizeof(double)));
+}
+
+// State slots: [0, nl) main/outer, [nl, 2nl) inner, [2nl, 3nl) post/utility, 3nl spare utility.
+SolverState* st_main(ffth_plan* P, int l) { return P->d_state + l; }
+SolverState* st_inner(ffth_plan* P, int l) { return P->d_state + P->nloads + l; }
+SolverState* st_post(ffth_plan* P, int l) { return P->d_state + 2 * P->nloads + l; }
+
+// Descriptor slots (roles x nloads).
+enum Role { R_MAIN = 0, R_MAIN_DELTA = 1, R_INNER = 2, R_POST = 3, R_THETA = 4, R_UTIL = 5, R_PROJ = 6 };
+int desc_slot(ffth_plan* P, Role r, int l) { return (int)r * P->nloads + l; }
+const Desc* dptr(ffth_plan* P, Role r) { return P->d_desc + desc_slot(P, r, 0); }
+// the 6 order-1 displacement descriptors live after the role blocks
+int util6_slot(ffth_plan* P, int J) { return 7 * P->nloads + J; }
+
+// ---- kernel timing ---------------------------------------------------------
+enum Cat { C_XF32 = 0, C_Y32, C_Z32, C_XI32, C_XF64, C_Y64, C_Z64, C_XI64, C_FIN, C_POINT, NCAT };
+const char* const CAT_NAMES[NCAT] = {"xfwd_f32", "ypass_f32", "zpass_f32", "xinv_f32", "xfwd_f64",
+                                     "ypass_f64", "zpass_f64", "xinv_f64", "finalize", "pointwise"};
+
+hipEvent_t take_event(ffth_plan* P) {
+  if (P->pool.empty()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  hipEvent_t e = P->pool.back();
+  P->pool.pop_back();
+  return e;
+}
+
+// Bracket one launch: call before (returns the record index or -1) and after.
+int prof_begin(ffth_plan* P, int cat) {
+  if (!P->prof) return -1;
+  ffth_plan::Rec r{cat, take_event(P), take_event(P)};
+  if (!r.a || !r.b) return -1;
+  (void)hipEventRecord(r.a, P->stream);
+  P->recs.push_back(r);
+  return (int)P->recs.size() - 1;
+}
+void prof_end(ffth_plan* P, int idx) {
+  if (idx >= 0) (void)hipEventRecord(P->recs[idx].b, P->stream);
+}
+// Called after a stream synchronisation: fold finished records into the totals.
+void prof_flush(ffth_plan* P) {
+  for (auto& r : P->recs) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      P->prof_ms[r.cat] += ms;
+      P->prof_n[r.cat] += 1;
+    }
+    P->pool.push_back(r.a);
+    P->pool.push_back(r.b);
+  }
+  P->recs.clear();
+}
+
+struct ProfScope {
+  ffth_plan* P;
+  int idx;
+  ProfScope(ffth_plan* p, int cat) : P(p), idx(prof_begin(p, cat)) {}
+  ~ProfScope() { prof_end(P, idx); }
+};
+
+Desc base_desc(ffth_plan* P, int l) {
+  Desc d;
+  std::memset(&d, 0, sizeof(d));
+  d.phase = P->phase;
+  d.mat64 = P->mat64;
+  d.mat32 = P->mat32;
+  d.spec = spec_ptr(P, l);
+  d.part_f = part_ptr(P, 2 * l);
+  d.part_i = part_ptr(P, 2 * l + 1);
+  d.nc = 6;
+  return d;
+}
+
+SolverState make_state(double tol, int max_iter, double guard_eps, int active) {
+  SolverState s;
+  std::memset(&s, 0, sizeof(s));
+  s.tol = tol;
+  s.max_iter = max_iter;
+  s.guard_eps = guard_eps;
+  s.gscale = -1.0;
+  s.active = active;
+  s.first = 1;
+  s.res = 1.0;
+  return s;
+}
+
+ffth_status upload_descs(ffth_plan* P) {
+  HIPCHK(hipMemcpyAsync(P->d_desc, P->h_desc.data(), P->h_desc.size() * sizeof(Desc), hipMemcpyHostToDevice,
+                        P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  return FFTH_OK;
+}
+
+ffth_status upload_states(ffth_plan* P, const std::vector<SolverState>& s, int first_slot) {
+  HIPCHK(hipMemcpyAsync(P->d_state + first_slot, s.data(), s.size() * sizeof(SolverState), hipMemcpyHostToDevice,
+                        P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  return FFTH_OK;
+}
+
+ffth_status read_states(ffth_plan* P) {
+  HIPCHK(hipMemcpyAsync(P->h_state, P->d_state, P->L.nstate * sizeof(SolverState), hipMemcpyDeviceToHost,
+                        P->stream));
+  HIPCHK(hipStreamSynchronize(P->stream));
+  prof_flush(P);
+  return FFTH_OK;
+}
+
+// ---- pass launchers -------------------------------------------------------
+
+template <typename T> int xblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->nx64 : P->nx32; }
+
+template <typename T> ffth_status xfwd(ffth_plan* P, const Desc* d, int nb, int mode) {
+  ProfScope ps(P, sizeof(T) == 8 ? C_XF64 : C_XF32);
+  HIPCHK(Launch<T>::xfwd(P->n[2], P->iso, dim3(xblocks<T>(P), nb), P->stream, d, mode, P->rows, P->nvox, P->lam0,
+                         P->mu0));
+  return FFTH_OK;
+}
+
+template <typename T> ffth_status yzy(ffth_plan* P, const Desc* d, int nb, int op) {
+  const int ncols = P->h * 6;
+  const int cw = Launch<T>::y_cols(P->n[1]);
+  const int ntiles = (ncols + cw - 1) / cw;
+  const int cy = sizeof(T) == 8 ? C_Y64 : C_Y32, cz = sizeof(T) == 8 ? C_Z64 : C_Z32;
+  {
+    ProfScope ps(P, cy);
+    HIPCHK(Launch<T>::ypass(P->n[1], dim3(P->n[0] * ntiles, nb), P->stream, d, -1, ncols, ntiles));
+  }
+  const long M = (long)P->n[1] * P->h;
+  const int tk = Launch<T>::z_cols(P->n[0]);
+  const double scale = 1.0 / (double)P->nvox;
+  {
+    ProfScope ps(P, cz);
+    HIPCHK(Launch<T>::zpass(P->n[0], dim3((int)((M + tk - 1) / tk), nb), P->stream, d, op, P->n[1], P->h,
+                            P->lam0, P->mu0, scale));
+  }
+  {
+    ProfScope ps(P, cy);
+    HIPCHK(Launch<T>::ypass(P->n[1], dim3(P->n[0] * ntiles, nb), P->stream, d, +1, ncols, ntiles));
+  }
+  return FFTH_OK;
+}
+
+template <typename T> ffth_status xinv(ffth_plan* P, const Desc* d, int nb, int mode) {
+  ProfScope ps(P, sizeof(T) == 8 ? C_XI64 : C_XI32);
+  HIPCHK(Launch<T>::xinv(P->n[2], P->iso, dim3(xblocks<T>(P), nb), P->stream, d, mode, P->rows, P->nvox, P->lam0,
+                         P->mu0));
+  return FFTH_OK;
+}
+
+ffth_status fin(ffth_plan* P, const Desc* d, int nb, int op, int nblk_f, int nblk_i) {
+  ProfScope ps(P, C_FIN);
+  HIPCHK(launch_finalize(nb, P->stream, d, op, nblk_f, nblk_i, P->lam0, P->mu0));
+  return FFTH_OK;
+}
+
+// One full operator application: x-fwd(mode) [fin alpha] y z y x-inv(mode) fin(op)
+template <typename T>
+ffth_status apply(ffth_plan* P, const Desc* d, int nb, int xf, int spec_op, int xi, int fin_op) {
+  ffth_status s;
+  if ((s = xfwd<T>(P, d, nb, xf)) != FFTH_OK) return s;
+  if (xf == XF_CG && (s = fin(P, d, nb, FIN_CG_ALPHA, xblocks<T>(P), 0)) != FFTH_OK) return s;
+  if ((s = yzy<T>(P, d, nb, spec_op)) != FFTH_OK) return s;
+  if ((s = xinv<T>(P, d, nb, xi)) != FFTH_OK) return s;
+  if (fin_op >= 0 && (s = fin(P, d, nb, fin_op, xblocks<T>(P), xblocks<T>(P))) != FFTH_OK) return s;
+  return FFTH_OK;
+}
+
+bool any_active(ffth_plan* P, int first, int count) {
+  for (int i = 0; i < count; ++i)
+    if (P->h_state[first + i].active) return true;
+  return false;
+}
+
+// ---- solve loops ----------------------------------------------------------
+
+// Iterate a plain (single precision level) scheme on descriptors d with
+// states in slots [0, nl).  The iterate must hold zero on entry.
+template <typename T> ffth_status run_plain(ffth_plan* P, const Desc* d, int nl) {
+  const ffth_opts& o = P->opts;
+  ffth_status s;
+  // pass 0: x = b = -Gamma0 * P_rhs, ||b||, zero right-hand-side guard
+  if ((s = apply<T>(P, d, nl, XF_LS, OP_GAMMA, XI_BS, FIN_LS_FIRST)) != FFTH_OK) return s;
+  if (o.scheme == FFTH_CG) {
+    // r0 = b - A b = LS(x) - x
+    if ((s = apply<T>(P, d, nl, XF_LS, OP_GAMMA, XI_RESID, FIN_RESID_INIT)) != FFTH_OK) return s;
+  }
+  if ((s = read_states(P)) != FFTH_OK) return s;
+  int it = 0;
+  while (it < o.max_iter && any_active(P, 0, nl)) {
+    const int k = std::min(o.check_every, o.max_iter - it);
+    for (int j = 0; j < k; ++j) {
+      if (o.scheme == FFTH_BASIC) s = apply<T>(P, d, nl, XF_LS, OP_GAMMA, XI_BS, FIN_BS);
+      else s = apply<T>(P, d, nl, XF_CG, OP_GAMMA, XI_CG, FIN_CG_BETA);
+      if (s != FFTH_OK) return s;
+    }
+    it += k;
+    if ((s = read_states(P)) != FFTH_OK) return s;
+  }
+  return FFTH_OK;
+}
+
+// FP32 inner solves under an FP64 defect-correction loop.  Outer states in
+// [0, nl), inner states in [nl, 2nl).  eps (the FP64 iterate) zero on entry.
+ffth_status run_mixed(ffth_plan* P, int nl) {
+  const ffth_opts& o = P->opts;
+  ffth_status s;
+  int inner_total = 0;
+  for (int outer = 0; outer < o.max_outer; ++outer) {
+    // r = b - A x in FP64 (x += delta fused).  The first sweep has x = 0 and
+    // r = b, compatible: it goes straight to the FP32 inner right-hand side.
+    // Later sweeps keep r in FP64 and split it with the projection
+    // P = Gamma0 C0: the compatible part feeds the inner solve, the rest
+    // (minus the incompatible round-off of x) is applied to x directly.
+    if (outer == 0) s = apply<double>(P, dptr(P, R_MAIN), nl, XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER);
+    else s = apply<double>(P, dptr(P, R_MAIN_DELTA), nl, XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER_P);
+    if (s != FFTH_OK) return s;
+    if ((s = read_states(P)) != FFTH_OK) return s;
+    if (!any_active(P, 0, nl)) break;
+    if (outer == o.max_outer - 1) break;  // no sweep left to apply another correction
+    if (outer > 0 && (s = apply<double>(P, dptr(P, R_PROJ), nl, XF_C0, OP_GAMMA, XI_PROJ, FIN_PROJ)) != FFTH_OK)
+      return s;
+    const Desc* di = dptr(P, R_INNER);
+    for (int l = 0; l < nl; ++l) {
+      const size_t bytes = (size_t)P->nvox * 6 * sizeof(float);
+      if (o.scheme == FFTH_CG) {
+        HIPCHK(hipMemsetAsync(f32_ptr(P, l, 0), 0, bytes, P->stream));          // delta = 0
+      } else {
+        HIPCHK(hipMemcpyAsync(f32_ptr(P, l, 0), f32_ptr(P, l, 1), bytes, hipMemcpyDeviceToDevice, P->stream));
+      }
+    }
+    int it = 0;
+    while (inner_total + it < o.max_iter && any_active(P, nl, nl)) {
+      const int k = std::min(o.check_every, o.max_iter - inner_total - it);
+      for (int j = 0; j < k; ++j) {
+        if (o.scheme == FFTH_BASIC) s = apply<float>(P, di, nl, XF_MATVEC, OP_GAMMA, XI_BS_INNER, FIN_BS);
+        else s = apply<float>(P, di, nl, XF_CG, OP_GAMMA, XI_CG, FIN_CG_BETA);
+        if (s != FFTH_OK) return s;
+      }
+      it += k;
+      if ((s = read_states(P)) != FFTH_OK) return s;
+    }
+    inner_total += it;
+    if (inner_total >= o.max_iter) {
+      // budget spent: one more FP64 sweep applies the last correction
+      const Desc* dmd = dptr(P, R_MAIN_DELTA);
+      if ((s = apply<double>(P, dmd, nl, XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER_P)) != FFTH_OK) return s;
+      if ((s = read_states(P)) != FFTH_OK) return s;
+      break;
+    }
+  }
+  return FFTH_OK;
+}
+
+ffth_status check_plan(ffth_plan* P, int nloads) {
+  if (!P) {
+    g_last_error = "null plan";
+    return FFTH_ERR_INVALID;
+  }
+  if (nloads < 1 || nloads > P->nloads) {
+    g_last_error = "nloads outside [1, plan nloads]";
+    return FFTH_ERR_INVALID;
+  }
+  return FFTH_OK;
+}
+
+// Fill descriptors of roles MAIN/MAIN_DELTA/INNER/POST for nl loads.
+void build_solve_descs(ffth_plan* P, int nl, const double* E, double* eps, bool order1) {
+  const ffth_opts& o = P->opts;
+  for (int l = 0; l < nl; ++l) {
+    Desc m = base_desc(P, l);
+    if (E) {
+      const double* e = E + 6 * l;
+      for (int c = 0; c < 6; ++c) m.E[c] = c < 3 ? e[c] : 0.5 * e[c];
+    }
+    m.P = order1 ? Pfield(P, l) : nullptr;
+    m.st = st_main(P, l);
+    m.st2 = st_inner(P, l);
+    double* epsl = eps + (size_t)l * 6 * P->nvox;
+    if (o.precision == FFTH_FP64) {
+      m.x = epsl;
+      if (o.scheme == FFTH_CG) {
+        m.r = f64_ptr(P, l, 0);
+        m.p = f64_ptr(P, l, 1);
+      }
+    } else if (o.precision == FFTH_FP32) {
+      m.x = f32_ptr(P, l, 0);
+      if (o.scheme == FFTH_CG) {
+        m.r = f32_ptr(P, l, 1);
+        m.p = f32_ptr(P, l, 2);
+      }
+    } else {  // MIXED: outer FP64 pass
+      m.x = epsl;
+      m.r = f32_ptr(P, l, 1);
+      m.r_f32 = 1;
+    }
+    P->h_desc[desc_slot(P, R_MAIN, l)] = m;
+    Desc md = m;
+    Desc pr = m;
+    if (o.precision == FFTH_MIXED) {
+      // later sweeps: x += delta fused; full FP64 residual kept for its projection
+      md.delta = f32_ptr(P, l, 0);
+      md.r = f64_ptr(P, l, 0);
+      md.r_f32 = 0;
+      pr.r = f64_ptr(P, l, 0);
+      pr.out = f32_ptr(P, l, 1);
+    }
+    P->h_desc[desc_slot(P, R_MAIN_DELTA, l)] = md;
+    P->h_desc[desc_slot(P, R_PROJ, l)] = pr;
+    Desc in = base_desc(P, l);
+    in.st = st_inner(P, l);
+    if (o.precision == FFTH_MIXED) {
+      in.x = f32_ptr(P, l, 0);                                  // delta
+      in.r = f32_ptr(P, l, 1);                                  // inner residual / rhs
+      in.p = o.scheme == FFTH_CG ? f32_ptr(P, l, 2) : nullptr;  // CG direction
+    }
+    P->h_desc[desc_slot(P, R_INNER, l)] = in;
+    Desc post = base_desc(P, l);
+    post.st = st_post(P, l);
+    post.x = epsl;
+    for (int c = 0; c < 6; ++c) post.E[c] = m.E[c];
+    post.P = m.P;
+    if (o.precision == FFTH_FP32) {
+      post.x = f32_ptr(P, l, 0);  // widened into eps first (k_widen reads x, writes out)
+      post.out = epsl;
+    }
+    P->h_desc[desc_slot(P, R_POST, l)] = post;
+  }
+}
+
+// Run the solve for nl loads whose descriptors are built, then fill results.
+ffth_status solve_common(ffth_plan* P, int nl, double* eps, ffth_result* res, double t0, const double* gmean) {
+  const ffth_opts& o = P->opts;
+  ffth_status s;
+  const double guard = o.precision == FFTH_FP32 ? 1e-6 : 1e-14;
+  std::vector<SolverState> sts(3 * P->nloads + 1);
+  for (int l = 0; l < P->nloads; ++l) {
+    sts[l] = make_state(o.tol, o.precision == FFTH_MIXED ? o.max_outer : o.max_iter, guard, l < nl);
+    sts[P->nloads + l] = make_state(o.inner_tol, o.max_iter, 1e-6, 0);
+    sts[2 * P->nloads + l] = make_state(0, 1, 0, 1);
+  }
+  sts[3 * P->nloads] = make_state(0, 1, 0, 1);
+  // keep the order-1 guard scales computed by the right-hand-side builder
+  if (gmean) {
+    if ((s = read_states(P)) != FFTH_OK) return s;
+    for (int l = 0; l < nl; ++l) sts[l].gscale = P->h_state[2 * P->nloads + l].gscale;
+  }
+  if ((s = upload_states(P, sts, 0)) != FFTH_OK) return s;
+  // zero the iterate
+  for (int l = 0; l < nl; ++l) {
+    const Desc& m = P->h_desc[desc_slot(P, R_MAIN, l)];
+    const size_t bytes = (size_t)P->nvox * 6 * (o.precision == FFTH_FP32 ? sizeof(float) : sizeof(double));
+    HIPCHK(hipMemsetAsync(m.x, 0, bytes, P->stream));
+  }
+  if (o.precision == FFTH_FP64) s = run_plain<double>(P, dptr(P, R_MAIN), nl);
+  else if (o.precision == FFTH_FP32) s = run_plain<float>(P, dptr(P, R_MAIN), nl);
+  else s = run_mixed(P, nl);
+  if (s != FFTH_OK) return s;
+  // zero-rhs guard: eps = 0 exactly
+  if ((s = read_states(P)) != FFTH_OK) return s;
+  for (int l = 0; l < nl; ++l)
+    if (P->h_state[l].flag == FLAG_ZERO_RHS) {
+      const Desc& m = P->h_desc[desc_slot(P, R_MAIN, l)];
+      const size_t bytes = (size_t)P->nvox * 6 * (o.precision == FFTH_FP32 ? sizeof(float) : sizeof(double));
+      HIPCHK(hipMemsetAsync(m.x, 0, bytes, P->stream));
+    }
+  const Desc* dp = dptr(P, R_POST);
+  if (o.precision == FFTH_FP32) {
+    ProfScope ps(P, C_POINT);
+    HIPCHK(launch_widen(nl, P->stream, dp, (long)P->nvox * 6));
+  }
+  // mean stress: the post descriptors read eps (FP64)
+  if (o.precision == FFTH_FP32) {
+    for (int l = 0; l < nl; ++l) P->h_desc[desc_slot(P, R_POST, l)].x = eps + (size_t)l * 6 * P->nvox;
+    if ((s = upload_descs(P)) != FFTH_OK) return s;
+  }
+  const int nms = ms_blocks(P->nvox);
+  {
+    ProfScope ps(P, C_POINT);
+    HIPCHK(launch_mean_stress(P->iso, nms, nl, P->stream, dp, P->nvox));
+  }
+  if ((s = fin(P, dp, nl, FIN_SUMS_I, 0, nms)) != FFTH_OK) return s;
+  if ((s = read_states(P)) != FFTH_OK) return s;
+  const double secs =
+      std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count() - t0;
+  ffth_status worst = FFTH_OK;
+  for (int l = 0; l < nl; ++l) {
+    const SolverState& m = P->h_state[l];
+    const SolverState& in = P->h_state[P->nloads + l];
+    const SolverState& po = P->h_state[2 * P->nloads + l];
+    ffth_result& r = res[l];
+    std::memset(&r, 0, sizeof(r));
+    if (m.flag == FLAG_CONVERGED || m.flag == FLAG_ZERO_RHS) r.status = FFTH_OK;
+    else if (m.flag == FLAG_DIVERGED) r.status = FFTH_ERR_DIVERGED;
+    else r.status = FFTH_ERR_NOT_CONVERGED;
+    if (o.precision == FFTH_MIXED) {
+      r.iters = in.total;
+      r.outer_iters = m.iters;
+      r.fp64_applications = m.fp64_apps;
+    } else {
+      r.iters = m.iters;
+      r.fp64_applications = o.precision == FFTH_FP64 ? m.iters + (o.scheme == FFTH_CG ? 2 : 1) : 0;
+    }
+    r.residual = m.res;
+    for (int c = 0; c < 6; ++c) r.mean_stress[c] = po.sums[c] / (double)P->nvox;
+    if (gmean)
+      for (int c = 0; c < 3; ++c) r.g_mean[c] = gmean[3 * l + c];
+    r.seconds = secs;
+    if (r.status != FFTH_OK && worst == FFTH_OK) worst = (ffth_status)r.status;
+  }
+  return worst;
+}
+
+double now_s() { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); }
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+void ffth_default_opts(ffth_opts* o) {
+  if (!o) return;
+  o->scheme = FFTH_CG;
+  o->precision = FFTH_MIXED;
+  o->tol = 1e-8;
+  o->max_iter = 20000;
+  o->inner_tol = 1e-4;
+  o->max_outer = 12;
+  o->check_every = 8;
+}
+
+int32_t ffth_size_supported(int32_t n) { return size_supported(n) ? 1 : 0; }
+
+size_t ffth_workspace_bytes(const int32_t n[3], int32_t nphases, int32_t nloads, int32_t order, const ffth_opts* o) {
+  if (!n || !o || nloads < 1 || nphases < 1 || nphases > 65535 || (order != 0 && order != 1)) return 0;
+  for (int d = 0; d < 3; ++d)
+    if (!size_supported(n[d])) return 0;
+  if (!opts_valid(*o)) return 0;
+  int nn[3] = {n[0], n[1], n[2]};
+  return make_layout(nn, nphases, nloads, order, *o).total;
+}
+
+const char* ffth_status_string(ffth_status s) {
+  switch (s) {
+    case FFTH_OK: return "ok";
+    case FFTH_ERR_INVALID: return "invalid argument";
+    case FFTH_ERR_OOM: return "workspace too small";
+    case FFTH_ERR_NOT_CONVERGED: return "not converged";
+    case FFTH_ERR_DIVERGED: return "diverged";
+    case FFTH_ERR_DEVICE: return "device error";
+    case FFTH_ERR_BUSY: return "busy";
+    case FFTH_ERR_CANCELLED: return "cancelled";
+  }
+  return "unknown status";
+}
+
+const char* ffth_last_error(void) { return g_last_error.c_str(); }
+
+ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_opts* o, int32_t nloads, int32_t order,
+                             void* workspace, size_t bytes, void* hip_stream) {
+  g_last_error.clear();
+  if (!out || !p || !o || !workspace) {
+    g_last_error = "null argument";
+    return FFTH_ERR_INVALID;
+  }
+  *out = nullptr;
+  if (((uintptr_t)workspace) % ALIGN) {
+    g_last_error = "workspace not 256-byte aligned";
+    return FFTH_ERR_INVALID;
+  }
+  for (int d = 0; d < 3; ++d)
+    if (!size_supported(p->n[d])) {
+      g_last_error = "unsupported grid size " + std::to_string(p->n[d]);
+      return FFTH_ERR_INVALID;
+    }
+  if (p->nphases < 1 || p->nphases > 65535 || !p->phase || ((p->lame == nullptr) == (p->stiffness == nullptr))) {
+    g_last_error = "bad phase table";
+    return FFTH_ERR_INVALID;
+  }
+  if (!(p->mu0 != 0.0) || !(p->lambda0 + 2.0 * p->mu0 != 0.0) || !std::isfinite(p->mu0) ||
+      !std::isfinite(p->lambda0)) {
+    g_last_error = "reference medium needs mu0 != 0 and lambda0 + 2 mu0 != 0";
+    return FFTH_ERR_INVALID;
+  }
+  if (o->scheme == FFTH_CG && !(p->mu0 > 0.0 && 3.0 * p->lambda0 + 2.0 * p->mu0 > 0.0)) {
+    g_last_error = "CG needs a positive definite reference medium";
+    return FFTH_ERR_INVALID;
+  }
+  if (!opts_valid(*o) || nloads < 1 || (order != 0 && order != 1)) {
+    g_last_error = "bad options";
+    return FFTH_ERR_INVALID;
+  }
+  int nn[3] = {p->n[0], p->n[1], p->n[2]};
+  Layout L = make_layout(nn, p->nphases, nloads, order, *o);
+  if (bytes < L.total) {
+    g_last_error = "workspace needs " + std::to_string(L.total) + " bytes";
+    return FFTH_ERR_OOM;
+  }
+  ffth_plan* P = new ffth_plan();
+  for (int d = 0; d < 3; ++d) P->n[d] = p->n[d];
+  P->nvox = (long)p->n[0] * p->n[1] * p->n[2];
+  P->h = p->n[2] / 2;
+  P->rows = (long)p->n[0] * p->n[1];
+  P->nph = p->nphases;
+  P->iso = p->lame != nullptr;
+  P->lam0 = p->lambda0;
+  P->mu0 = p->mu0;
+  P->phase = p->phase;
+  P->stream = (hipStream_t)hip_stream;
+  P->nloads = nloads;
+  P->order = order;
+  P->opts = *o;
+  P->ws = (char*)workspace;
+  P->L = L;
+  P->mat64 = (double*)(P->ws + L.mat64);
+  P->mat32 = (float*)(P->ws + L.mat32);
+  P->d_desc = (Desc*)(P->ws + L.desc);
+  P->d_state = (SolverState*)(P->ws + L.state);
+  P->nx64 = x_blocks(p->n[0], p->n[1], p->n[2], true);
+  P->nx32 = x_blocks(p->n[0], p->n[1], p->n[2], false);
+  P->h_desc.assign(L.ndesc, Desc{});
+  if (!hip_ok(hipHostMalloc((void**)&P->h_state, L.nstate * sizeof(SolverState), hipHostMallocDefault),
+              "hipHostMalloc")) {
+    delete P;
+    return FFTH_ERR_DEVICE;
+  }
+  // material tables
+  std::vector<double> m64((size_t)p->nphases * 72, 0.0);
+  double m0[36];
+  iso_to_m(p->lambda0, p->mu0, m0);
+  for (int ph = 0; ph < p->nphases; ++ph) {
+    if (P->iso) {
+      const double lam = p->lame[2 * ph], mu = p->lame[2 * ph + 1];
+      m64[ph * 4 + 0] = lam;
+      m64[ph * 4 + 1] = mu;
+      m64[ph * 4 + 2] = lam - p->lambda0;
+      m64[ph * 4 + 3] = mu - p->mu0;
+    } else {
+      double m[36];
+      voigt21_to_m(p->stiffness + 21 * ph, m);
+      for (int i = 0; i < 36; ++i) {
+        m64[ph * 72 + i] = m[i];
+        m64[ph * 72 + 36 + i] = m[i] - m0[i];
+      }
+    }
+  }
+  std::vector<float> m32(m64.size());
+  for (size_t i = 0; i < m64.size(); ++i) m32[i] = (float)m64[i];
+  bool ok = hip_ok(hipMemcpyAsync(P->mat64, m64.data(), m64.size() * 8, hipMemcpyHostToDevice, P->stream), "copy") &&
+            hip_ok(hipMemcpyAsync(P->mat32, m32.data(), m32.size() * 4, hipMemcpyHostToDevice, P->stream), "copy");
+  // phase ids must index the table
+  int* dmax = (int*)(P->ws + L.misc);
+  ok = ok && hip_ok(hipMemsetAsync(dmax, 0, sizeof(int), P->stream), "memset") &&
+       hip_ok(launch_phase_max(P->stream, p->phase, P->nvox, dmax), "phase check");
+  int hmax = 0;
+  ok = ok && hip_ok(hipMemcpyAsync(&hmax, dmax, sizeof(int), hipMemcpyDeviceToHost, P->stream), "copy") &&
+       hip_ok(hipStreamSynchronize(P->stream), "sync");
+  if (!ok) {
+    (void)hipHostFree(P->h_state);
+    delete P;
+    return FFTH_ERR_DEVICE;
+  }
+  if (hmax >= p->nphases) {
+    g_last_error = "phase id " + std::to_string(hmax) + " >= nphases";
+    (void)hipHostFree(P->h_state);
+    delete P;
+    return FFTH_ERR_INVALID;
+  }
+  *out = P;
+  return FFTH_OK;
+}
+
+ffth_status ffth_plan_destroy(ffth_plan* P) {
+  if (!P) return FFTH_ERR_INVALID;
+  (void)hipStreamSynchronize(P->stream);
+  prof_flush(P);
+  for (hipEvent_t e : P->pool) (void)hipEventDestroy(e);
+  (void)hipHostFree(P->h_state);
+  delete P;
+  return FFTH_OK;
+}
+
+ffth_status ffth_solve_order0(ffth_plan* P, int32_t nloads, const double* E, double* eps, ffth_result* res) {
+  g_last_error.clear();
+  ffth_status s = check_plan(P, nloads);
+  if (s != FFTH_OK) return s;
+  if (!E || !eps || !res) {
+    g_last_error = "null argument";
+    return FFTH_ERR_INVALID;
+  }
+  const double t0 = now_s();
+  build_solve_descs(P, nloads, E, eps, false);
+  if ((s = upload_descs(P)) != FFTH_OK) return s;
+  return solve_common(P, nloads, eps, res, t0, nullptr);
+}
+
+namespace {
+
+// Order-1 polarization P_l = p_2 + theta_2 for nl gradient loads (X1 built).
+ffth_status build_order1_rhs(ffth_plan* P, int nl, const double* eps0, const double* G, double* const* Pout,
+                             std::vector<double>& gmean) {
+  ffth_status s;
+  for (int l = 0; l < nl; ++l) {
+    Desc d = base_desc(P, l);
+    d.st = st_post(P, l);
+    for (int i = 0; i < 18; ++i) d.G[i] = G[18 * l + i];
+    d.io = Pout[l];          // p_2 out (then theta accumulated)
+    d.p = gfield(P, l);      // g out
+    P->h_desc[desc_slot(P, R_POST, l)] = d;
+    Desc t = base_desc(P, l);
+    t.st = st_post(P, l);
+    t.io = gfield(P, l);     // copy-in g (3 components)
+    t.nc = 3;
+    t.out = Pout[l];         // accumulate theta into P
+    P->h_desc[desc_slot(P, R_THETA, l)] = t;
+  }
+  if ((s = upload_descs(P)) != FFTH_OK) return s;
+  std::vector<SolverState> post(nl, make_state(0, 1, 0, 1));
+  if ((s = upload_states(P, post, 2 * P->nloads)) != FFTH_OK) return s;
+  const int nms = ms_blocks(P->nvox);
+  {
+    ProfScope ps(P, C_POINT);
+    HIPCHK(launch_order1_point(P->iso, nms, nl, P->stream, dptr(P, R_POST), eps0, X1field(P), P->nvox));
+  }
+  if ((s = fin(P, dptr(P, R_POST), nl, FIN_O1RHS, 0, nms)) != FFTH_OK) return s;
+  const Desc* dt = dptr(P, R_THETA);
+  if ((s = xfwd<double>(P, dt, nl, XF_COPY)) != FFTH_OK) return s;
+  if ((s = yzy<double>(P, dt, nl, OP_THETA)) != FFTH_OK) return s;
+  // the accumulate pass stores 6 components
+  for (int l = 0; l < nl; ++l) P->h_desc[desc_slot(P, R_THETA, l)].nc = 6;
+  if ((s = upload_descs(P)) != FFTH_OK) return s;
+  if ((s = xinv<double>(P, dt, nl, XI_ACCUM)) != FFTH_OK) return s;
+  if ((s = read_states(P)) != FFTH_OK) return s;
+  gmean.assign(3 * nl, 0.0);
+  for (int l = 0; l < nl; ++l)
+    for (int c = 0; c < 3; ++c) gmean[3 * l + c] = P->h_state[2 * P->nloads + l].sums[2 + c] / (double)P->nvox;
+  return FFTH_OK;
+}
+
+ffth_status make_x1(ffth_plan* P, const double* eps0) {
+  // Forward + spectral operator, then inverse, one corrector at a time so
+  // that a single spectrum buffer suffices.
+  ffth_status s;
+  for (int J = 0; J < 6; ++J) {
+    Desc d = base_desc(P, 0);
+    d.part_f = part_ptr(P, 2 * P->nloads);
+    d.part_i = part_ptr(P, 2 * P->nloads + 1);
+    d.st = P->d_state + 3 * P->nloads;
+    d.io = (void*)(eps0 + (size_t)J * 6 * P->nvox);
+    d.out = X1field(P) + (size_t)J * 3 * P->nvox;
+    d.nc = 6;
+    P->h_desc[util6_slot(P, J)] = d;
+  }
+  if ((s = upload_descs(P)) != FFTH_OK) return s;
+  std::vector<SolverState> u(1, make_state(0, 1, 0, 1));
+  if ((s = upload_states(P, u, 3 * P->nloads)) != FFTH_OK) return s;
+  for (int J = 0; J < 6; ++J) {
+    const Desc* d = P->d_desc + util6_slot(P, J);
+    if ((s = xfwd<double>(P, d, 1, XF_COPY)) != FFTH_OK) return s;
+    if ((s = yzy<double>(P, d, 1, OP_DISP)) != FFTH_OK) return s;
+    // store 3 components: a second descriptor copy with nc = 3
+    Desc d3 = P->h_desc[util6_slot(P, J)];
+    d3.nc = 3;
+    P->h_desc[util6_slot(P, J)] = d3;
+    if ((s = upload_descs(P)) != FFTH_OK) return s;
+    if ((s = xinv<double>(P, d, 1, XI_STORE)) != FFTH_OK) return s;
+    HIPCHK(hipStreamSynchronize(P->stream));
+  }
+  return FFTH_OK;
+}
+
+}  // namespace
+
+ffth_status ffth_solve_order1(ffth_plan* P, const double* eps0_six, int32_t nloads, const double* G, double* eps,
+                              ffth_result* res) {
+  g_last_error.clear();
+  ffth_status s = check_plan(P, nloads);
+  if (s != FFTH_OK) return s;
+  if (P->order != 1) {
+    g_last_error = "plan was created for order 0";
+    return FFTH_ERR_INVALID;
+  }
+  if (!eps0_six || !G || !eps || !res) {
+    g_last_error = "null argument";
+    return FFTH_ERR_INVALID;
+  }
+  const double t0 = now_s();
+  if ((s = make_x1(P, eps0_six)) != FFTH_OK) return s;
+  std::vector<double*> pout(nloads);
+  for (int l = 0; l < nloads; ++l) pout[l] = Pfield(P, l);
+  std::vector<double> gmean;
+  if ((s = build_order1_rhs(P, nloads, eps0_six, G, pout.data(), gmean)) != FFTH_OK) return s;
+  build_solve_descs(P, nloads, nullptr, eps, true);
+  if ((s = upload_descs(P)) != FFTH_OK) return s;
+  return solve_common(P, nloads, eps, res, t0, gmean.data());
+}
+
+ffth_status ffth_green_apply(ffth_plan* P, const double* tau, double* eta, int32_t precision) {
+  g_last_error.clear();
+  ffth_status s = check_plan(P, 1);
+  if (s != FFTH_OK) return s;
+  if (!tau || !eta || (precision != FFTH_FP64 && precision != FFTH_FP32)) {
+    g_last_error = "bad argument";
+    return FFTH_ERR_INVALID;
+  }
+  Desc d = base_desc(P, 0);
+  d.st = P->d_state + 3 * P->nloads;
+  d.io = (void*)tau;
+  d.out = eta;
+  d.nc = 6;
+  P->h_desc[desc_slot(P, R_UTIL, 0)] = d;
+  if ((s = upload_descs(P)) != FFTH_OK) return s;
+  std::vector<SolverState> u(1, make_state(0, 1, 0, 1));
+  if ((s = upload_states(P, u, 3 * P->nloads)) != FFTH_OK) return s;
+  const Desc* dd = dptr(P, R_UTIL);
+  if (precision == FFTH_FP64) {
+    if ((s = xfwd<double>(P, dd, 1, XF_COPY)) != FFTH_OK) return s;
+    if ((s = yzy<double>(P, dd, 1, OP_GAMMA)) != FFTH_OK) return s;
+    if ((s = xinv<double>(P, dd, 1, XI_STORE)) != FFTH_OK) return s;
+  } else {
+    if ((s = xfwd<float>(P, dd, 1, XF_COPY)) != FFTH_OK) return s;
+    if ((s = yzy<float>(P, dd, 1, OP_GAMMA)) != FFTH_OK) return s;
+    if ((s = xinv<float>(P, dd, 1, XI_STORE)) != FFTH_OK) return s;
+  }
+  HIPCHK(hipStreamSynchronize(P->stream));
+  return FFTH_OK;
+}
+
+ffth_status ffth_displacement(ffth_plan* P, const double* eps, double* u) {
+  g_last_error.clear();
+  ffth_status s = check_plan(P, 1);
+  if (s != FFTH_OK) return s;
+  if (!eps || !u) {
+    g_last_error = "null argument";
+    return FFTH_ERR_INVALID;
+  }
+  Desc d = base_desc(P, 0);
+  d.st = P->d_state + 3 * P->nloads;
+  d.io = (void*)eps;
+  d.out = u;
+  d.nc = 6;
+  P->h_desc[desc_slot(P, R_UTIL, 0)] = d;
+  if ((s = upload_descs(P)) != FFTH_OK) return s;
+  std::vector<SolverState> st(1, make_state(0, 1, 0, 1));
+  if ((s = upload_states(P, st, 3 * P->nloads)) != FFTH_OK) return s;
+  const Desc* dd = dptr(P, R_UTIL);
+  if ((s = xfwd<double>(P, dd, 1, XF_COPY)) != FFTH_OK) return s;
+  if ((s = yzy<double>(P, dd, 1, OP_DISP)) != FFTH_OK) return s;
+  P->h_desc[desc_slot(P, R_UTIL, 0)].nc = 3;
+  if ((s = upload_descs(P)) != FFTH_OK) return s;
+  if ((s = xinv<double>(P, dd, 1, XI_STORE)) != FFTH_OK) return s;
+  HIPCHK(hipStreamSynchronize(P->stream));
+  return FFTH_OK;
+}
+
+ffth_status ffth_order1_rhs(ffth_plan* P, const double* eps0_six, const double* G, double* Pout, double* g_mean) {
+  g_last_error.clear();
+  ffth_status s = check_plan(P, 1);
+  if (s != FFTH_OK) return s;
+  if (P->order != 1) {
+    g_last_error = "plan was created for order 0";
+    return FFTH_ERR_INVALID;
+  }
+  if (!eps0_six || !G || !Pout) {
+    g_last_error = "null argument";
+    return FFTH_ERR_INVALID;
+  }
+  if ((s = make_x1(P, eps0_six)) != FFTH_OK) return s;
+  std::vector<double> gm;
+  double* po[1] = {Pout};
+  if ((s = build_order1_rhs(P, 1, eps0_six, G, po, gm)) != FFTH_OK) return s;
+  if (g_mean)
+    for (int c = 0; c < 3; ++c) g_mean[c] = gm[c];
+  HIPCHK(hipStreamSynchronize(P->stream));
+  return FFTH_OK;
+}
+
+ffth_status ffth_profile_enable(ffth_plan* P, int32_t on) {
+  if (!P) return FFTH_ERR_INVALID;
+  HIPCHK(hipStreamSynchronize(P->stream));
+  prof_flush(P);
+  for (int c = 0; c < NCAT; ++c) {
+    P->prof_ms[c] = 0.0;
+    P->prof_n[c] = 0;
+  }
+  P->prof = on != 0;
+  return FFTH_OK;
+}
+
+ffth_status ffth_profile_read(ffth_plan* P, int32_t category, int64_t* launches, double* ms) {
+  if (!P || category < 0 || category >= NCAT || !launches || !ms) return FFTH_ERR_INVALID;
+  HIPCHK(hipStreamSynchronize(P->stream));
+  prof_flush(P);
+  *launches = P->prof_n[category];
+  *ms = P->prof_ms[category];
+  return FFTH_OK;
+}
+
+const char* ffth_profile_name(int32_t category) {
+  return (category >= 0 && category < NCAT) ? CAT_NAMES[category] : "";
+}
+
+}  // extern "C"

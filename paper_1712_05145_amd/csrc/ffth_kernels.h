@@ -1,0 +1,520 @@
+// HIP kernels of one iteration of the Moulinec-Suquet Basic Scheme / its CG
+// form (Algorithm 1 and eq. (6) of arXiv:1712.05145), organised as five
+// HBM-streaming passes over a half spectrum stored as [n0][n1][n2/2][6]
+// complex:
+//
+//   x-pass (forward)   constitutive law / polarization tau (Algorithm 1, first
+//                      step; eq. (2)) fused with the real-to-complex FFT along
+//                      the contiguous axis (two real components per complex FFT)
+//   y-pass             complex FFT along axis 1 (forward or inverse)
+//   z-pass             forward FFT along axis 0, the spectral operator (Green
+//                      operator below eq. (5) with eta_hat(0) = 0; theta of
+//                      eq. (12); displacement recovery from eq. (1)), inverse FFT
+//   y-pass (inverse)
+//   x-pass (inverse)   complex-to-real FFT fused with the Basic Scheme / CG
+//                      update and the residual reductions
+//
+// All FFTs run in LDS (mixed-radix Stockham, fft_device.h).  Block tile
+// sizes are compile-time functions of the axis length and precision.
+#pragma once
+#include "fft_device.h"
+#include "ffth_types.h"
+
+namespace ffth {
+
+constexpr int NT = 256;   // threads per block of every FFT pass
+
+constexpr int pow2_floor(int v) {
+  int p = 1;
+  while (p * 2 <= v) p *= 2;
+  return p;
+}
+template <typename T> constexpr int x_rows(int n) {
+  int r = (sizeof(T) == 4 ? 1024 : 512) / n;
+  return r < 1 ? 1 : pow2_floor(r);
+}
+template <typename T> constexpr int y_cols(int n) {
+  int c = (sizeof(T) == 4 ? 4096 : 2048) / n;
+  int cap = sizeof(T) == 4 ? 16 : 8;
+  c = c > cap ? cap : c;
+  return c < 1 ? 1 : pow2_floor(c);
+}
+template <typename T> constexpr int z_cols(int n) {
+  int c = (sizeof(T) == 4 ? 1024 : 512) / n;
+  c = c > 16 ? 16 : c;
+  return c < 1 ? 1 : pow2_floor(c);
+}
+
+// ---------------------------------------------------------------------------
+// Constitutive law helpers.  Tensor-component vectors (11,22,33,23,13,12).
+// Isotropic table row: (lam, mu, lam - lam0, mu - mu0).  Generic table row:
+// M (36, maps tensor components to stress) followed by M - M0 (36).
+// ---------------------------------------------------------------------------
+template <typename T> __device__ __forceinline__ const T* mat_of(const Desc& d);
+template <> __device__ __forceinline__ const float* mat_of<float>(const Desc& d) { return d.mat32; }
+template <> __device__ __forceinline__ const double* mat_of<double>(const Desc& d) { return d.mat64; }
+
+// out = (C or C - C0)(phase) : e
+template <typename T, bool ISO>
+__device__ __forceinline__ void apply_mat(const T* mat, int ph, bool delta, const T (&e)[6], T (&out)[6]) {
+  if constexpr (ISO) {
+    const T lam = mat[ph * 4 + (delta ? 2 : 0)];
+    const T mu2 = T(2) * mat[ph * 4 + (delta ? 3 : 1)];
+    const T tr = e[0] + e[1] + e[2];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) out[c] = mu2 * e[c] + (c < 3 ? lam * tr : T(0));
+  } else {
+    const T* m = mat + ph * 72 + (delta ? 36 : 0);
+#pragma unroll
+    for (int a = 0; a < 6; ++a) {
+      T s = 0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b) s += m[a * 6 + b] * e[b];
+      out[a] = s;
+    }
+  }
+}
+
+template <typename T> __device__ __forceinline__ T frob_w(const T (&a)[6], const T (&b)[6]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + T(2) * (a[3] * b[3] + a[4] * b[4] + a[5] * b[5]);
+}
+// C0 inner product density lam0 tr a tr b + 2 mu0 a:b
+__device__ __forceinline__ double c0_ip(double lam0, double mu0, const double (&a)[6], const double (&b)[6]) {
+  const double ta = a[0] + a[1] + a[2], tb = b[0] + b[1] + b[2];
+  const double ab = a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + 2.0 * (a[3] * b[3] + a[4] * b[4] + a[5] * b[5]);
+  return lam0 * ta * tb + 2.0 * mu0 * ab;
+}
+
+// ---------------------------------------------------------------------------
+// x-pass, forward: polarization + real-to-complex FFT along axis 2.
+// ---------------------------------------------------------------------------
+template <typename T, int N2, bool ISO>
+__global__ __launch_bounds__(NT) void k_xfwd(const Desc* __restrict__ descs, int mode, long rows_total,
+                                             long nvox, double lam0, double mu0) {
+  constexpr int ROWS = x_rows<T>(N2);
+  constexpr int RS = N2 + N2 / 16;
+  constexpr int H = N2 / 2;
+  __shared__ C2<T> z[ROWS * 3 * RS];
+  __shared__ C2<T> tw[N2];
+  const Desc& d = descs[blockIdx.y];
+  if (!d.st->active) return;
+  build_twiddles<T, N2, NT>(tw);
+  const long row0 = (long)blockIdx.x * ROWS;
+  const T* mat = mat_of<T>(d);
+  double acc0 = 0.0;
+  const T beta = (T)d.st->beta;
+  const bool first = d.st->first != 0;
+
+  for (int v = threadIdx.x; v < ROWS * N2; v += NT) {
+    const int rr = v / N2, i2 = v % N2;
+    const long row = row0 + rr;
+    T tau[6] = {0, 0, 0, 0, 0, 0};
+    if (row < rows_total) {
+      const long vox = row * N2 + i2;
+      const int ph = d.phase[vox];
+      if (mode == XF_LS) {
+        T x[6] = {0, 0, 0, 0, 0, 0};
+        T* xp = (T*)d.x;
+        if (xp) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) x[c] = xp[c * nvox + vox];
+          if (d.delta) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+              x[c] += (T)d.delta[c * nvox + vox];
+              xp[c * nvox + vox] = x[c];
+            }
+          }
+        }
+        T pr[6];
+        if (d.P) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) pr[c] = (T)d.P[c * nvox + vox];
+        } else {
+          T e[6];
+#pragma unroll
+          for (int c = 0; c < 6; ++c) e[c] = (T)d.E[c];
+          apply_mat<T, ISO>(mat, ph, false, e, pr);
+        }
+        T dx[6];
+        apply_mat<T, ISO>(mat, ph, true, x, dx);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) tau[c] = pr[c] + dx[c];
+        acc0 += (double)frob_w(pr, pr);
+      } else if (mode == XF_MATVEC) {
+        const T* vp = (const T*)d.x;
+        T x[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) x[c] = vp[c * nvox + vox];
+        apply_mat<T, ISO>(mat, ph, true, x, tau);
+      } else if (mode == XF_CG) {
+        const T* rp = (const T*)d.r;
+        T* pp = (T*)d.p;
+        T p[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          const T rv = rp[c * nvox + vox];
+          p[c] = first ? rv : rv + beta * pp[c * nvox + vox];
+          pp[c * nvox + vox] = p[c];
+        }
+        apply_mat<T, ISO>(mat, ph, true, p, tau);
+        T cp[6];
+        apply_mat<T, ISO>(mat, ph, false, p, cp);
+        acc0 += (double)frob_w(p, cp);
+      } else if (mode == XF_C0) {
+        // tau = C0 : v (projection onto compatible fields: -Gamma0 * C0 v)
+        const T* vp = (const T*)d.r;
+        T v[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) v[c] = vp[c * nvox + vox];
+        const T tr = (T)lam0 * (v[0] + v[1] + v[2]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) tau[c] = T(2) * (T)mu0 * v[c] + (c < 3 ? tr : T(0));
+      } else {  // XF_COPY
+        const double* ip = (const double*)d.io;
+#pragma unroll
+        for (int c = 0; c < 6; ++c)
+          if (c < d.nc) tau[c] = (T)ip[c * nvox + vox];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) z[(rr * 3 + q) * RS + padx<true>(i2)] = C2<T>{tau[2 * q], tau[2 * q + 1]};
+  }
+  __syncthreads();
+  lds_fft<T, N2, ROWS * 3, NT, 1, RS, false, true, -1>(z, tw);
+
+  C2<T>* spec = (C2<T>*)d.spec;
+  for (int v = threadIdx.x; v < ROWS * H * 6; v += NT) {
+    const int rr = v / (H * 6), rem = v % (H * 6);
+    const long row = row0 + rr;
+    if (row >= rows_total) continue;
+    const int k = rem / 6, c = rem % 6, q = c >> 1;
+    const C2<T>* zr = z + (rr * 3 + q) * RS;
+    const C2<T> z1 = zr[padx<true>(k)];
+    const C2<T> z2 = conj(zr[padx<true>((N2 - k) % N2)]);
+    C2<T> o;
+    if ((c & 1) == 0) o = (z1 + z2) * T(0.5);
+    else o = C2<T>{(z1.y - z2.y) * T(0.5), -(z1.x - z2.x) * T(0.5)};
+    spec[row * (H * 6) + rem] = o;
+  }
+  double sums[1] = {acc0};
+  block_sums<1, NT>(sums, d.part_f + (long)blockIdx.x * NRED);
+}
+
+// ---------------------------------------------------------------------------
+// x-pass, inverse: complex-to-real FFT along axis 2 + update + reductions.
+// ---------------------------------------------------------------------------
+template <typename T, int N2, bool ISO>
+__global__ __launch_bounds__(NT) void k_xinv(const Desc* __restrict__ descs, int mode, long rows_total, long nvox,
+                                             double lam0, double mu0) {
+  constexpr int ROWS = x_rows<T>(N2);
+  constexpr int RS = N2 + N2 / 16;
+  constexpr int H = N2 / 2;
+  __shared__ C2<T> z[ROWS * 3 * RS];
+  __shared__ C2<T> tw[N2];
+  const Desc& d = descs[blockIdx.y];
+  if (!d.st->active) return;
+  build_twiddles<T, N2, NT>(tw);
+  const long row0 = (long)blockIdx.x * ROWS;
+  const C2<T>* spec = (const C2<T>*)d.spec;
+
+  for (int v = threadIdx.x; v < ROWS * H * 3; v += NT) {
+    const int rr = v / (H * 3), rem = v % (H * 3);
+    const int k = rem / 3, q = rem % 3;
+    const long row = row0 + rr;
+    C2<T> a = {0, 0}, b = {0, 0};
+    if (row < rows_total) {
+      const C2<T>* s = spec + row * (H * 6) + k * 6 + 2 * q;
+      a = s[0];
+      b = s[1];
+    }
+    C2<T>* zr = z + (rr * 3 + q) * RS;
+    if (k == 0) {
+      zr[padx<true>(0)] = C2<T>{a.x, b.x};
+      zr[padx<true>(H)] = C2<T>{0, 0};
+    } else {
+      zr[padx<true>(k)] = C2<T>{a.x - b.y, a.y + b.x};
+      zr[padx<true>(N2 - k)] = C2<T>{a.x + b.y, b.x - a.y};
+    }
+  }
+  __syncthreads();
+  lds_fft<T, N2, ROWS * 3, NT, 1, RS, false, true, +1>(z, tw);
+
+  const T alpha = (T)d.st->alpha;
+  double acc0 = 0.0, acc1 = 0.0;
+  for (int v = threadIdx.x; v < ROWS * N2; v += NT) {
+    const int rr = v / N2, i2 = v % N2;
+    const long row = row0 + rr;
+    if (row >= rows_total) continue;
+    const long vox = row * N2 + i2;
+    T eta[6];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      const C2<T> w = z[(rr * 3 + q) * RS + padx<true>(i2)];
+      eta[2 * q] = w.x;
+      eta[2 * q + 1] = w.y;
+    }
+    if (mode == XI_STORE || mode == XI_ACCUM) {
+      double* op = (double*)d.out;
+#pragma unroll
+      for (int c = 0; c < 6; ++c)
+        if (c < d.nc) op[c * nvox + vox] = (mode == XI_ACCUM ? op[c * nvox + vox] : 0.0) + (double)eta[c];
+    } else if (mode == XI_BS) {
+      T* xp = (T*)d.x;
+      T df[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        df[c] = eta[c] - xp[c * nvox + vox];
+        xp[c * nvox + vox] = eta[c];
+      }
+      acc0 += (double)frob_w(df, df);
+    } else if (mode == XI_RESID) {
+      const T* xp = (const T*)d.x;
+      double r[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) r[c] = (double)eta[c] - (double)xp[c * nvox + vox];
+      if (d.r_f32) {
+        float* rp = (float*)d.r;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) rp[c * nvox + vox] = (float)r[c];
+      } else {
+        T* rp = (T*)d.r;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) rp[c * nvox + vox] = (T)r[c];
+      }
+      acc0 += r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + 2.0 * (r[3] * r[3] + r[4] * r[4] + r[5] * r[5]);
+      acc1 += c0_ip(lam0, mu0, r, r);
+    } else if (mode == XI_BS_INNER) {
+      T* xp = (T*)d.x;
+      const T* rp = (const T*)d.r;
+      T df[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const T nv = rp[c * nvox + vox] + eta[c];
+        df[c] = nv - xp[c * nvox + vox];
+        xp[c * nvox + vox] = nv;
+      }
+      acc0 += (double)frob_w(df, df);
+    } else if (mode == XI_PROJ) {
+      // eta = -P r.  Compatible part r_c = -eta goes to the FP32 inner right-hand
+      // side; the rest, r - r_c = -(incompatible part of x), is applied to x.
+      T* xp = (T*)d.x;
+      const T* rp = (const T*)d.r;
+      float* op = (float*)d.out;
+      double rc[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        rc[c] = -(double)eta[c];
+        const T rv = rp[c * nvox + vox];
+        xp[c * nvox + vox] += rv - (T)rc[c];
+        op[c * nvox + vox] = (float)rc[c];
+      }
+      acc0 += rc[0] * rc[0] + rc[1] * rc[1] + rc[2] * rc[2] + 2.0 * (rc[3] * rc[3] + rc[4] * rc[4] + rc[5] * rc[5]);
+      acc1 += c0_ip(lam0, mu0, rc, rc);
+    } else {  // XI_CG: q = p - eta; x += alpha p; r -= alpha q
+      T* xp = (T*)d.x;
+      T* rp = (T*)d.r;
+      const T* pp = (const T*)d.p;
+      double r[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const T pv = pp[c * nvox + vox];
+        const T qv = pv - eta[c];
+        xp[c * nvox + vox] += alpha * pv;
+        const T rv = rp[c * nvox + vox] - alpha * qv;
+        rp[c * nvox + vox] = rv;
+        r[c] = (double)rv;
+      }
+      acc0 += c0_ip(lam0, mu0, r, r);
+      acc1 += r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + 2.0 * (r[3] * r[3] + r[4] * r[4] + r[5] * r[5]);
+    }
+  }
+  double sums[2] = {acc0, acc1};
+  block_sums<2, NT>(sums, d.part_i + (long)blockIdx.x * NRED);
+}
+
+// ---------------------------------------------------------------------------
+// y-pass: complex FFT along axis 1, in place.  Block = one i0 plane, CW
+// consecutive columns of the [n1][n2/2 * 6] plane.
+// ---------------------------------------------------------------------------
+template <typename T, int N1, int DIR>
+__device__ __forceinline__ void ypass_body(C2<T>* base, int ncols, int c0, C2<T>* buf, const C2<T>* tw) {
+  constexpr int CW = y_cols<T>(N1);
+  for (int v = threadIdx.x; v < N1 * CW; v += NT) {
+    const int i1 = v / CW, col = v % CW;
+    buf[v] = (c0 + col < ncols) ? base[(long)i1 * ncols + col] : C2<T>{0, 0};
+  }
+  __syncthreads();
+  lds_fft<T, N1, CW, NT, CW, 1, true, false, DIR>(buf, tw);
+  for (int v = threadIdx.x; v < N1 * CW; v += NT) {
+    const int i1 = v / CW, col = v % CW;
+    if (c0 + col < ncols) base[(long)i1 * ncols + col] = buf[v];
+  }
+}
+
+template <typename T, int N1>
+__global__ __launch_bounds__(NT) void k_ypass(const Desc* __restrict__ descs, int dir, int ncols, int ntiles) {
+  constexpr int CW = y_cols<T>(N1);
+  __shared__ C2<T> buf[N1 * CW];
+  __shared__ C2<T> tw[N1];
+  const Desc& d = descs[blockIdx.y];
+  if (!d.st->active) return;
+  build_twiddles<T, N1, NT>(tw);
+  const long i0 = blockIdx.x / ntiles;
+  const int c0 = (blockIdx.x % ntiles) * CW;
+  C2<T>* base = (C2<T>*)d.spec + i0 * N1 * (long)ncols + c0;
+  if (dir < 0) ypass_body<T, N1, -1>(base, ncols, c0, buf, tw);
+  else ypass_body<T, N1, +1>(base, ncols, c0, buf, tw);
+}
+
+// ---------------------------------------------------------------------------
+// z-pass: forward FFT along axis 0, spectral operator, inverse FFT.
+// Block = TK consecutive (i1, k2) columns x 6 components x all i0.
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void spectral_op(int op, T (&in)[6][2], T (&out)[6][2], T k0, T k1, T k2, double lam0,
+                                            double mu0, T scale) {
+  const T kk = k0 * k0 + k1 * k1 + k2 * k2;
+  const T inv = T(1) / sqrt(kk);
+  const T n[3] = {k0 * inv, k1 * inv, k2 * inv};
+  if (op == OP_GAMMA) {
+    // eta_hat = -[ (n x v + v x n) / (2 mu0) - c2 (n.v) n x n ],  v = tau_hat n
+    const T c2 = (T)((lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0)));
+    const T h = (T)(0.5 / mu0);
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      const T t0 = in[0][ri], t1 = in[1][ri], t2 = in[2][ri], t3 = in[3][ri], t4 = in[4][ri], t5 = in[5][ri];
+      const T v0 = t0 * n[0] + t5 * n[1] + t4 * n[2];
+      const T v1 = t5 * n[0] + t1 * n[1] + t3 * n[2];
+      const T v2 = t4 * n[0] + t3 * n[1] + t2 * n[2];
+      const T s = (n[0] * v0 + n[1] * v1 + n[2] * v2) * c2;
+      out[0][ri] = -scale * (T(2) * h * n[0] * v0 - s * n[0] * n[0]);
+      out[1][ri] = -scale * (T(2) * h * n[1] * v1 - s * n[1] * n[1]);
+      out[2][ri] = -scale * (T(2) * h * n[2] * v2 - s * n[2] * n[2]);
+      out[3][ri] = -scale * (h * (n[1] * v2 + n[2] * v1) - s * n[1] * n[2]);
+      out[4][ri] = -scale * (h * (n[0] * v2 + n[2] * v0) - s * n[0] * n[2]);
+      out[5][ri] = -scale * (h * (n[0] * v1 + n[1] * v0) - s * n[0] * n[1]);
+    }
+  } else if (op == OP_THETA) {
+    // theta_hat_ij = (i/|xi|) [ n_i n_j (g.n) - (g_i n_j + n_i g_j) ],  |xi| = 2 pi |k|
+    const T f = scale * inv * (T)(0.5 / 3.14159265358979323846);
+    T w[6][2];
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      const T g0 = in[0][ri], g1 = in[1][ri], g2 = in[2][ri];
+      const T gn = g0 * n[0] + g1 * n[1] + g2 * n[2];
+      w[0][ri] = n[0] * n[0] * gn - T(2) * g0 * n[0];
+      w[1][ri] = n[1] * n[1] * gn - T(2) * g1 * n[1];
+      w[2][ri] = n[2] * n[2] * gn - T(2) * g2 * n[2];
+      w[3][ri] = n[1] * n[2] * gn - (g1 * n[2] + n[1] * g2);
+      w[4][ri] = n[0] * n[2] * gn - (g0 * n[2] + n[0] * g2);
+      w[5][ri] = n[0] * n[1] * gn - (g0 * n[1] + n[0] * g1);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {  // multiply by i f
+      out[c][0] = -f * w[c][1];
+      out[c][1] = f * w[c][0];
+    }
+  } else {  // OP_DISP: u_hat = (-i/|xi|) [ 2 eps_hat n - n (n . eps_hat n) ]
+    const T f = scale * inv * (T)(0.5 / 3.14159265358979323846);
+    T w[3][2];
+#pragma unroll
+    for (int ri = 0; ri < 2; ++ri) {
+      const T t0 = in[0][ri], t1 = in[1][ri], t2 = in[2][ri], t3 = in[3][ri], t4 = in[4][ri], t5 = in[5][ri];
+      const T v0 = t0 * n[0] + t5 * n[1] + t4 * n[2];
+      const T v1 = t5 * n[0] + t1 * n[1] + t3 * n[2];
+      const T v2 = t4 * n[0] + t3 * n[1] + t2 * n[2];
+      const T s = n[0] * v0 + n[1] * v1 + n[2] * v2;
+      w[0][ri] = T(2) * v0 - n[0] * s;
+      w[1][ri] = T(2) * v1 - n[1] * s;
+      w[2][ri] = T(2) * v2 - n[2] * s;
+    }
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {  // multiply by -i f
+      out[c][0] = f * w[c][1];
+      out[c][1] = -f * w[c][0];
+    }
+    out[3][0] = out[3][1] = out[4][0] = out[4][1] = out[5][0] = out[5][1] = T(0);
+  }
+}
+
+template <typename T, int N0, int DIR>
+__device__ __forceinline__ void zfft(C2<T>* buf, const C2<T>* tw) {
+  constexpr int W = z_cols<T>(N0) * 6;
+  lds_fft<T, N0, W, NT, W, 1, true, false, DIR>(buf, tw);
+}
+
+template <typename T, int N0>
+__global__ __launch_bounds__(NT) void k_zpass(const Desc* __restrict__ descs, int op, int n1, int h, double lam0,
+                                              double mu0, double scale) {
+  constexpr int TK = z_cols<T>(N0);
+  constexpr int W = TK * 6;
+  __shared__ C2<T> buf[N0 * W];
+  __shared__ C2<T> tw[N0];
+  const Desc& d = descs[blockIdx.y];
+  if (!d.st->active) return;
+  build_twiddles<T, N0, NT>(tw);
+  const long M = (long)n1 * h;
+  const long m0 = (long)blockIdx.x * TK;
+  C2<T>* spec = (C2<T>*)d.spec;
+  for (int v = threadIdx.x; v < N0 * W; v += NT) {
+    const int i0 = v / W, w = v % W;
+    buf[v] = (m0 + w / 6 < M) ? spec[((long)i0 * M + m0) * 6 + w] : C2<T>{0, 0};
+  }
+  __syncthreads();
+  zfft<T, N0, -1>(buf, tw);
+  for (int v = threadIdx.x; v < N0 * TK; v += NT) {
+    const int k0 = v / TK, col = v % TK;
+    const long m = m0 + col;
+    if (m >= M) continue;
+    const int k1 = (int)(m / h), k2 = (int)(m % h);
+    const bool nyq = ((N0 % 2 == 0) && k0 == N0 / 2) || ((n1 % 2 == 0) && k1 == n1 / 2);
+    const int k0s = k0 < (N0 + 1) / 2 ? k0 : k0 - N0;
+    const int k1s = k1 < (n1 + 1) / 2 ? k1 : k1 - n1;
+    C2<T>* e = buf + k0 * W + col * 6;
+    T in[6][2], out[6][2];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      in[c][0] = e[c].x;
+      in[c][1] = e[c].y;
+    }
+    if (nyq || (k0s == 0 && k1s == 0 && k2 == 0)) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) out[c][0] = out[c][1] = T(0);
+    } else {
+      spectral_op<T>(op, in, out, (T)k0s, (T)k1s, (T)k2, lam0, mu0, (T)scale);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e[c] = C2<T>{out[c][0], out[c][1]};
+  }
+  __syncthreads();
+  zfft<T, N0, +1>(buf, tw);
+  for (int v = threadIdx.x; v < N0 * W; v += NT) {
+    const int i0 = v / W, w = v % W;
+    if (m0 + w / 6 < M) spec[((long)i0 * M + m0) * 6 + w] = buf[v];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Finalize: fixed-order sum of the block partials of one batch entry, then
+// the scalar update of its iteration state.  One block per entry.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_finalize(const Desc* __restrict__ descs, int op, int nblk_f, int nblk_i,
+                                                 double lam0, double mu0);
+
+// Volume averages of sigma = P_rhs + C:x (or C:(E + x)): 6 sums per block.
+template <bool ISO>
+__global__ __launch_bounds__(NT) void k_mean_stress(const Desc* __restrict__ descs, long nvox);
+
+// Order-1 pointwise right-hand side: P = C:sym(X1.G), g_i = sum_J c_J S^J_ij G_Jj.
+template <bool ISO>
+__global__ __launch_bounds__(NT) void k_order1_point(const Desc* __restrict__ descs, const double* __restrict__ eps0,
+                                                     const double* __restrict__ x1, long nvox);
+
+// out <- (double) x for FP32 x, n values.
+__global__ void k_widen(const Desc* __restrict__ descs, long n);
+
+// Largest phase id (validation of the problem input).
+__global__ void k_phase_max(const uint16_t* __restrict__ phase, long n, int* out);
+
+}  // namespace ffth

@@ -1,0 +1,287 @@
+// Finalize, volume-average and order-1 pointwise kernels (FP64).
+#include "ffth_kernels.h"
+#include "ffth_launch.h"
+
+namespace ffth {
+
+__device__ static void fin_check(SolverState* st) {
+  const double r = st->res;
+  if (!(r == r) || r > 1e6) {
+    st->flag = FLAG_DIVERGED;
+    st->active = 0;
+  } else if (r < st->tol) {
+    st->flag = FLAG_CONVERGED;
+    st->active = 0;
+  } else if (st->iters >= st->max_iter) {
+    st->active = 0;  // flag stays RUNNING: not converged
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_finalize(const Desc* __restrict__ descs, int op, int nblk_f, int nblk_i,
+                                                 double lam0, double mu0) {
+  const Desc& d = descs[blockIdx.x];
+  SolverState* st = d.st;
+  if (!st->active) return;
+  __shared__ double sf[NRED], si[NRED];
+  double af[NRED], ai[NRED];
+#pragma unroll
+  for (int k = 0; k < NRED; ++k) {
+    double a = 0.0, b = 0.0;
+    for (int i = threadIdx.x; i < nblk_f; i += NT) a += d.part_f[(long)i * NRED + k];
+    for (int i = threadIdx.x; i < nblk_i; i += NT) b += d.part_i[(long)i * NRED + k];
+    af[k] = a;
+    ai[k] = b;
+  }
+  block_sums<NRED, NT>(af, sf);
+  block_sums<NRED, NT>(ai, si);
+  __syncthreads();
+  if (threadIdx.x != 0) return;
+  const double amu = fabs(mu0);
+  switch (op) {
+    case FIN_LS_FIRST: {
+      st->nb2 = si[0];
+      const double gs = st->gscale > 0.0 ? st->gscale : sqrt(sf[0]) / (2.0 * amu);
+      st->iters = 0;
+      st->first = 1;
+      st->res = 1.0;
+      if (sqrt(si[0]) <= st->guard_eps * gs) {
+        st->flag = FLAG_ZERO_RHS;
+        st->res = 0.0;
+        st->active = 0;
+      }
+      break;
+    }
+    case FIN_BS:
+      st->res = sqrt(si[0] / st->nb2);
+      st->iters++;
+      st->total++;
+      fin_check(st);
+      break;
+    case FIN_RESID_INIT:
+      st->rr = si[1];
+      st->res = sqrt(si[0] / st->nb2);
+      st->first = 1;
+      if (st->res < st->tol) {
+        st->flag = FLAG_CONVERGED;
+        st->active = 0;
+      }
+      break;
+    case FIN_CG_ALPHA: {
+      const double pq = sf[0];
+      if (!(pq > 0.0) || !(st->rr == st->rr)) {
+        st->flag = FLAG_DIVERGED;
+        st->active = 0;
+      } else {
+        st->alpha = st->rr / pq;
+      }
+      break;
+    }
+    case FIN_CG_BETA:
+      st->res = sqrt(si[1] / st->nb2);
+      st->iters++;
+      st->total++;
+      st->beta = si[0] / st->rr;
+      st->rr = si[0];
+      st->first = 0;
+      fin_check(st);
+      break;
+    case FIN_PROJ: {
+      // compatible residual projected: set up the FP32 inner solve
+      SolverState* in = d.st2;
+      st->fp64_apps++;
+      in->active = 1;
+      in->nb2 = si[0];
+      in->rr = si[1];
+      in->first = 1;
+      in->iters = 0;
+      in->flag = FLAG_RUNNING;
+      in->res = 1.0;
+      if (!(si[0] > 0.0)) in->active = 0;
+      break;
+    }
+    case FIN_OUTER:
+    case FIN_OUTER_P: {
+      SolverState* in = d.st2;
+      if (st->iters == 0) {
+        st->nb2 = si[0];
+        const double gs = st->gscale > 0.0 ? st->gscale : sqrt(sf[0]) / (2.0 * amu);
+        if (sqrt(si[0]) <= st->guard_eps * gs) {
+          st->flag = FLAG_ZERO_RHS;
+          st->res = 0.0;
+          st->active = 0;
+          in->active = 0;
+          break;
+        }
+      }
+      st->res = sqrt(si[0] / st->nb2);
+      st->iters++;
+      st->fp64_apps++;
+      if (!(st->res == st->res) || st->res > 1e6) {
+        st->flag = FLAG_DIVERGED;
+        st->active = 0;
+      } else if (st->res < st->tol) {
+        st->flag = FLAG_CONVERGED;
+        st->active = 0;
+      } else if (st->iters >= st->max_iter) {
+        st->active = 0;
+      }
+      if (!st->active) {
+        in->active = 0;
+      } else if (op == FIN_OUTER_P) {
+        in->active = 0;  // the projection pass sets the inner solve up
+      } else {
+        in->active = 1;
+        in->nb2 = si[0];
+        in->rr = si[1];
+        in->first = 1;
+        in->iters = 0;
+        in->flag = FLAG_RUNNING;
+        in->res = 1.0;
+      }
+      break;
+    }
+    case FIN_SUMS_I:
+      for (int k = 0; k < NRED; ++k) st->sums[k] = si[k];
+      break;
+    case FIN_O1RHS:
+      for (int k = 0; k < NRED; ++k) st->sums[k] = si[k];
+      st->gscale = (sqrt(si[0]) + sqrt(si[1])) / (2.0 * amu);
+      break;
+  }
+}
+
+template <bool ISO>
+__global__ __launch_bounds__(NT) void k_mean_stress(const Desc* __restrict__ descs, long nvox) {
+  const Desc& d = descs[blockIdx.y];
+  if (!d.st->active) return;
+  double acc[NRED] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const double* x = (const double*)d.x;
+  for (long vox = (long)blockIdx.x * NT + threadIdx.x; vox < nvox; vox += (long)gridDim.x * NT) {
+    const int ph = d.phase[vox];
+    double e[6], s[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e[c] = x[c * nvox + vox] + (d.P ? 0.0 : d.E[c]);
+    apply_mat<double, ISO>(d.mat64, ph, false, e, s);
+    if (d.P) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) s[c] += d.P[c * nvox + vox];
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) acc[c] += s[c];
+  }
+  block_sums<NRED, NT>(acc, d.part_i + (long)blockIdx.x * NRED);
+}
+
+template <bool ISO>
+__global__ __launch_bounds__(NT) void k_order1_point(const Desc* __restrict__ descs, const double* __restrict__ eps0,
+                                                     const double* __restrict__ x1, long nvox) {
+  const Desc& d = descs[blockIdx.y];
+  if (!d.st->active) return;
+  double acc[NRED] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double* pout = (double*)d.io;   // [6][N] p_2
+  double* gout = (double*)d.p;    // [3][N] g
+  const double mult[6] = {1, 1, 1, 2, 2, 2};
+  for (long vox = (long)blockIdx.x * NT + threadIdx.x; vox < nvox; vox += (long)gridDim.x * NT) {
+    const int ph = d.phase[vox];
+    double xg[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double g[3] = {0, 0, 0};
+#pragma unroll
+    for (int J = 0; J < 6; ++J) {
+      const double cj = mult[J];
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const double xv = cj * x1[(long)(J * 3 + m) * nvox + vox];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) xg[m][j] += xv * d.G[J * 3 + j];
+      }
+      // S^J = C : (E^J + eps^J), E^J the unit engineering load J as a tensor
+      double e[6], s[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) e[c] = eps0[((long)J * 6 + c) * nvox + vox] + (c == J ? (J < 3 ? 1.0 : 0.5) : 0.0);
+      apply_mat<double, ISO>(d.mat64, ph, false, e, s);
+      // full matrix rows of S from (11,22,33,23,13,12)
+      const double S[3][3] = {{s[0], s[5], s[4]}, {s[5], s[1], s[3]}, {s[4], s[3], s[2]}};
+#pragma unroll
+      for (int i = 0; i < 3; ++i)
+        g[i] += cj * (S[i][0] * d.G[J * 3 + 0] + S[i][1] * d.G[J * 3 + 1] + S[i][2] * d.G[J * 3 + 2]);
+    }
+    double sy[6] = {xg[0][0], xg[1][1], xg[2][2], 0.5 * (xg[1][2] + xg[2][1]), 0.5 * (xg[0][2] + xg[2][0]),
+                    0.5 * (xg[0][1] + xg[1][0])};
+    double p2[6];
+    apply_mat<double, ISO>(d.mat64, ph, false, sy, p2);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) pout[c * nvox + vox] = p2[c];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) gout[i * nvox + vox] = g[i];
+    acc[0] += frob_w(p2, p2);
+    acc[1] += g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    acc[2] += g[0];
+    acc[3] += g[1];
+    acc[4] += g[2];
+  }
+  block_sums<NRED, NT>(acc, d.part_i + (long)blockIdx.x * NRED);
+}
+
+__global__ void k_widen(const Desc* __restrict__ descs, long n) {
+  const Desc& d = descs[blockIdx.y];
+  const float* src = (const float*)d.x;
+  double* dst = (double*)d.out;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    dst[i] = (double)src[i];
+}
+
+__global__ void k_phase_max(const uint16_t* __restrict__ phase, long n, int* out) {
+  int m = 0;
+  for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+    m = max(m, (int)phase[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, 64));
+  if ((threadIdx.x & 63) == 0) atomicMax(out, m);
+}
+
+template __global__ void k_mean_stress<true>(const Desc*, long);
+template __global__ void k_mean_stress<false>(const Desc*, long);
+template __global__ void k_order1_point<true>(const Desc*, const double*, const double*, long);
+template __global__ void k_order1_point<false>(const Desc*, const double*, const double*, long);
+
+}  // namespace ffth
+
+namespace ffth {
+
+bool size_supported(int n) {
+#define FFTH_CASE(N) if (n == N) return true;
+  FFTH_SIZES(FFTH_CASE)
+#undef FFTH_CASE
+  return false;
+}
+
+hipError_t launch_finalize(int nbatch, hipStream_t s, const Desc* d, int op, int nblk_f, int nblk_i, double lam0,
+                           double mu0) {
+  hipLaunchKernelGGL(k_finalize, dim3(nbatch), dim3(NT), 0, s, d, op, nblk_f, nblk_i, lam0, mu0);
+  return hipGetLastError();
+}
+
+hipError_t launch_mean_stress(bool iso, int nblk, int nbatch, hipStream_t s, const Desc* d, long nvox) {
+  if (iso) hipLaunchKernelGGL(k_mean_stress<true>, dim3(nblk, nbatch), dim3(NT), 0, s, d, nvox);
+  else hipLaunchKernelGGL(k_mean_stress<false>, dim3(nblk, nbatch), dim3(NT), 0, s, d, nvox);
+  return hipGetLastError();
+}
+
+hipError_t launch_order1_point(bool iso, int nblk, int nbatch, hipStream_t s, const Desc* d, const double* eps0,
+                               const double* x1, long nvox) {
+  if (iso) hipLaunchKernelGGL(k_order1_point<true>, dim3(nblk, nbatch), dim3(NT), 0, s, d, eps0, x1, nvox);
+  else hipLaunchKernelGGL(k_order1_point<false>, dim3(nblk, nbatch), dim3(NT), 0, s, d, eps0, x1, nvox);
+  return hipGetLastError();
+}
+
+hipError_t launch_phase_max(hipStream_t s, const uint16_t* phase, long n, int* out) {
+  hipLaunchKernelGGL(k_phase_max, dim3(512), dim3(256), 0, s, phase, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_widen(int nbatch, hipStream_t s, const Desc* d, long n) {
+  hipLaunchKernelGGL(k_widen, dim3(1024, nbatch), dim3(256), 0, s, d, n);
+  return hipGetLastError();
+}
+
+}  // namespace ffth

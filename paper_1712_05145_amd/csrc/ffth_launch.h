@@ -1,0 +1,37 @@
+// Host-side launchers of the templated FFT-pass kernels: a runtime axis
+// length selects the compile-time instantiation.
+#pragma once
+#include <hip/hip_runtime.h>
+#include "ffth_types.h"
+
+// Axis lengths with compiled FFT kernels.
+#define FFTH_SIZES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256) X(512)
+
+namespace ffth {
+
+bool size_supported(int n);
+
+template <typename T> struct Launch {
+  static int x_rows(int n);
+  static int y_cols(int n);
+  static int z_cols(int n);
+  static hipError_t xfwd(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox,
+                         double lam0, double mu0);
+  static hipError_t xinv(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox,
+                         double lam0, double mu0);
+  static hipError_t ypass(int n1, dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols, int ntiles);
+  static hipError_t zpass(int n0, dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h, double lam0,
+                          double mu0, double scale);
+};
+
+
+// non-templated kernels (ffth_kernels_common.hip)
+hipError_t launch_finalize(int nbatch, hipStream_t s, const Desc* d, int op, int nblk_f, int nblk_i, double lam0,
+                           double mu0);
+hipError_t launch_mean_stress(bool iso, int nblk, int nbatch, hipStream_t s, const Desc* d, long nvox);
+hipError_t launch_order1_point(bool iso, int nblk, int nbatch, hipStream_t s, const Desc* d, const double* eps0,
+                               const double* x1, long nvox);
+hipError_t launch_widen(int nbatch, hipStream_t s, const Desc* d, long n);
+hipError_t launch_phase_max(hipStream_t s, const uint16_t* phase, long n, int* out);
+
+}  // namespace ffth

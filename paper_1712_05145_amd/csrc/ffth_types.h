@@ -1,0 +1,71 @@
+// Plain-old-data structures shared by the host driver and the kernels.
+#pragma once
+#include <stdint.h>
+
+namespace ffth {
+
+// Per-load iteration state, resident in device memory.  The finalize kernel
+// is its only writer while a solve runs; the host reads it every few
+// iterations to decide whether to keep launching.
+struct SolverState {
+  double tol;        // relative residual to reach
+  double nb2;        // ||b||^2, the reference of the relative residual
+  double rr;         // CG: <r, r>_C0
+  double alpha, beta;
+  double res;        // last relative residual
+  double gscale;     // strain-like scale of the zero right-hand-side guard (<= 0: from ||P||)
+  double guard_eps;  // relative threshold of the guard
+  double sums[8];    // last finalized block sums (diagnostics, mean stress)
+  int32_t active;    // 1 while the load iterates; every kernel skips inactive loads
+  int32_t iters;     // iterations of the current solve
+  int32_t total;     // iterations over all solves sharing this state
+  int32_t flag;      // FLAG_*
+  int32_t first;     // CG: the next direction update takes p = r
+  int32_t max_iter;  // stop (unconverged) after this many iterations
+  int32_t fp64_apps; // FP64 operator applications (outer state only)
+  int32_t pad;
+};
+
+enum : int32_t { FLAG_RUNNING = 0, FLAG_CONVERGED = 1, FLAG_DIVERGED = 2, FLAG_ZERO_RHS = 3 };
+
+// Everything a kernel needs about one batch entry (one load case of one
+// RVE).  Kernels index an array of these with blockIdx.y (blockIdx.x for the
+// one-block-per-entry kernels).
+struct Desc {
+  const uint16_t* phase;   // [N] phase ids
+  const double* mat64;     // per phase: iso (lam, mu, lam-lam0, mu-mu0) or gen (M[36], M-M0[36])
+  const float* mat32;
+  void* x;                 // iterate (compute precision)
+  void* r;                 // residual (compute precision, or FP32 when r_f32)
+  void* p;                 // CG search direction
+  float* delta;            // FP32 correction fused into the FP64 residual pass (or null)
+  const double* P;         // stored right-hand-side polarization [6][N] (or null: C:E)
+  void* io;                // generic input field (copy-in mode; order-1 p_2 output)
+  void* out;               // generic output field (store / accumulate modes)
+  void* spec;              // half spectrum [n0][n1][n2/2][6] complex
+  double* part_f;          // [nblk][8] block sums of the forward x-pass
+  double* part_i;          // [nblk][8] block sums of the inverse x-pass / pointwise kernels
+  SolverState* st;         // gating state
+  SolverState* st2;        // secondary state (outer -> inner set-up)
+  double E[6];             // macroscopic strain, tensor components
+  double G[18];            // order-1 gradient load G[J*3 + j]
+  int32_t nc;              // components of io (3 or 6)
+  int32_t r_f32;           // residual stored as FP32
+  int32_t pad[2];
+};
+
+// x-pass (forward) modes
+enum : int32_t { XF_LS = 0, XF_MATVEC = 1, XF_CG = 2, XF_COPY = 3, XF_C0 = 4 };
+// x-pass (inverse) modes
+enum : int32_t { XI_STORE = 0, XI_ACCUM = 1, XI_BS = 2, XI_RESID = 3, XI_BS_INNER = 4, XI_CG = 5, XI_PROJ = 6 };
+// spectral operators of the z-pass
+enum : int32_t { OP_GAMMA = 0, OP_THETA = 1, OP_DISP = 2 };
+// finalize operations
+enum : int32_t {
+  FIN_LS_FIRST = 0, FIN_BS = 1, FIN_RESID_INIT = 2, FIN_CG_ALPHA = 3, FIN_CG_BETA = 4,
+  FIN_OUTER = 5, FIN_SUMS_I = 6, FIN_O1RHS = 7, FIN_OUTER_P = 8, FIN_PROJ = 9
+};
+
+constexpr int NRED = 8;   // doubles per block in the partial-sum arrays
+
+}  // namespace ffth

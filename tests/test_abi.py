@@ -1,0 +1,88 @@
+"""C-ABI library checks that need no GPU: it loads, exports every declared
+entry point, sizes workspaces and rejects invalid arguments before touching
+the device."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1712_05145_amd import ffth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    txt = open(os.path.join(ROOT, "include", "ffth.h")).read()
+    return sorted(set(re.findall(r"^\S.*?\b(ffth_[a-z0-9_]+)\s*\(", txt, flags=re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = ffth.load()
+    names = declared_functions()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(lib, n), n
+    assert sorted(s[0] for s in ffth.SIGNATURES) == names
+
+
+def test_supported_sizes_and_workspace():
+    for n in (4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512):
+        assert ffth.ffth_size_supported(n)
+    for n in (0, 1, 2, 3, 5, 7, 10, 1024):
+        assert not ffth.ffth_size_supported(n)
+    o = ffth.make_opts()
+    assert ffth.ffth_workspace_bytes((16, 16, 16), 2, 1, 0, o) > 0
+    assert ffth.ffth_workspace_bytes((16, 16, 10), 2, 1, 0, o) == 0
+    assert ffth.ffth_workspace_bytes((16, 16, 16), 0, 1, 0, o) == 0
+    # more loads, order 1 and FP64 CG all need more workspace
+    b1 = ffth.ffth_workspace_bytes((32, 32, 32), 2, 1, 0, o)
+    assert ffth.ffth_workspace_bytes((32, 32, 32), 2, 6, 0, o) > 5 * b1
+    assert ffth.ffth_workspace_bytes((32, 32, 32), 2, 1, 1, o) > b1
+    bad = ffth.make_opts(tol=-1.0)
+    assert ffth.ffth_workspace_bytes((16, 16, 16), 2, 1, 0, bad) == 0
+
+
+def _problem(n=(16, 16, 16), lam0=1.0, mu0=1.0):
+    pr = ffth.ffth_problem()
+    pr.n = (ctypes.c_int32 * 3)(*n)
+    pr.nphases = 1
+    pr.phase = 256            # never dereferenced: validation fails first
+    lame = np.array([1.0, 1.0])
+    pr._keep = lame
+    pr.lame = lame.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    pr.stiffness = None
+    pr.lambda0 = lam0
+    pr.mu0 = mu0
+    return pr
+
+
+@pytest.mark.parametrize("lam0,mu0,scheme,n", [
+    (1.0, 0.0, "basic", (16, 16, 16)),     # mu0 = 0
+    (-2.0, 1.0, "basic", (16, 16, 16)),    # lambda0 + 2 mu0 = 0
+    (1.0, -1.0, "cg", (16, 16, 16)),       # CG needs positive C0
+    (1.0, 1.0, "cg", (16, 16, 10)),        # unsupported size
+])
+def test_invalid_arguments_rejected_without_device(lam0, mu0, scheme, n):
+    lib = ffth.load()
+    pr = _problem(n, lam0, mu0)
+    o = ffth.make_opts(scheme=scheme)
+    plan = ctypes.c_void_p()
+    st = lib.ffth_plan_create(ctypes.byref(plan), ctypes.byref(pr), ctypes.byref(o), 1, 0,
+                              ctypes.c_void_p(4096), 1 << 30, None)
+    assert st == ffth.FFTH_ERR_INVALID
+    assert lib.ffth_last_error().decode() != ""
+
+
+def test_small_workspace_and_misaligned_rejected():
+    lib = ffth.load()
+    pr = _problem()
+    o = ffth.make_opts()
+    plan = ctypes.c_void_p()
+    assert lib.ffth_plan_create(ctypes.byref(plan), ctypes.byref(pr), ctypes.byref(o), 1, 0,
+                                ctypes.c_void_p(4096), 100, None) == ffth.FFTH_ERR_OOM
+    assert lib.ffth_plan_create(ctypes.byref(plan), ctypes.byref(pr), ctypes.byref(o), 1, 0,
+                                ctypes.c_void_p(4100), 1 << 30, None) == ffth.FFTH_ERR_INVALID
+    assert lib.ffth_plan_destroy(None) == ffth.FFTH_ERR_INVALID
+    assert lib.ffth_status_string(3).decode() == "not converged"

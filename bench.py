@@ -79,6 +79,8 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--scheme", default="cg", choices=["cg", "basic"])
     ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--inner-tol", type=float, default=1e-2,
+                    help="FP32 residual reduction between FP64 reliable updates")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=128)
@@ -106,8 +108,22 @@ def main():
 
     def make(precision, order, nloads):
         return ffth.Solver(phase, lam0, mu0, lame=lame, nloads=nloads, order=order, scheme=args.scheme,
-                           precision=precision, tol=args.tol, max_iter=50000, inner_tol=1e-4, max_outer=12,
+                           precision=precision, tol=args.tol, max_iter=50000, inner_tol=args.inner_tol, max_outer=30,
                            check_every=8, device=dev)
+
+    # achievable streaming bandwidth on this device (context for the roofline)
+    buf_a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+    buf_b = torch.empty_like(buf_a)
+    buf_b.copy_(buf_a)
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(10):
+        buf_b.copy_(buf_a)
+    ev1.record()
+    torch.cuda.synchronize()
+    copy_gbs = 10 * 2 * buf_a.numel() * 4 / (ev0.elapsed_time(ev1) * 1e-3) / 1e9
+    del buf_a, buf_b
+    log(f"device copy bandwidth {copy_gbs:.0f} GB/s")
 
     s0 = make("mixed", 0, 6)
     s1 = make("mixed", 1, 1)
@@ -169,7 +185,8 @@ def main():
     roofline = {"bound": "hbm", "kernel": cat, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                 "alg_bytes_per_voxel": ALG_BYTES_F32[cat], "units_per_launch": round(units / max(launches, 1), 3),
-                "avg_launch_ms": round(tot_ms / max(launches, 1), 4)}
+                "avg_launch_ms": round(tot_ms / max(launches, 1), 4),
+                "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "voxel-iters/s", "n_gpus": 1, "steps": args.steps,

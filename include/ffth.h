@@ -93,8 +93,10 @@ typedef struct {
   int32_t precision;          /* ffth_precision                                        */
   double tol;                 /* relative equilibrium residual to reach (e.g. 1e-8)    */
   int32_t max_iter;           /* iterations (FP64/FP32) or total inner iterations      */
-  double inner_tol;           /* MIXED: relative tolerance of each FP32 inner solve    */
-  int32_t max_outer;          /* MIXED: FP64 defect-correction sweeps                  */
+  double inner_tol;           /* MIXED: residual reduction of each FP32 inner solve     */
+  int32_t max_outer;          /* MIXED: FP64 defect-correction sweeps (each sweep after
+                                 the first also projects the residual onto compatible
+                                 fields, one FP32 operator application)                */
   int32_t check_every;        /* iterations between host reads of the convergence flags */
 } ffth_opts;
 
@@ -112,8 +114,8 @@ typedef struct {
 
 typedef struct ffth_plan ffth_plan;
 
-/* Default options: CG, MIXED, tol 1e-8, max_iter 20000, inner_tol 1e-4,
- * max_outer 12, check_every 8. */
+/* Default options: CG, MIXED, tol 1e-8, max_iter 20000, inner_tol 1e-2,
+ * max_outer 30, check_every 8. */
 void ffth_default_opts(ffth_opts *o);
 
 /* 1 if n (one axis length) is supported by the compiled FFT kernels. */

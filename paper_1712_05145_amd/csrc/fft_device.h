@@ -244,8 +244,10 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
+// out[r * stride] = block sum of v[r] (stride 1: NR consecutive doubles; stride =
+// number of blocks: slot-major partial arrays).
 template <int NR, int NT>
-__device__ __forceinline__ void block_sums(double (&v)[NR], double* out /* NR doubles */) {
+__device__ __forceinline__ void block_sums(double (&v)[NR], double* out, long stride = 1) {
   __shared__ double red[NT / 64][NR];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   __syncthreads();  // red may still be read by a previous call
@@ -259,7 +261,7 @@ __device__ __forceinline__ void block_sums(double (&v)[NR], double* out /* NR do
     double s = 0.0;
 #pragma unroll
     for (int i = 0; i < NT / 64; ++i) s += red[i][threadIdx.x];
-    out[threadIdx.x] = s;
+    out[threadIdx.x * stride] = s;
   }
 }
 

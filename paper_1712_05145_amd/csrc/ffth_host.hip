@@ -392,8 +392,10 @@ ffth_status run_mixed(ffth_plan* P, int nl) {
     if ((s = read_states(P)) != FFTH_OK) return s;
     if (!any_active(P, 0, nl)) break;
     if (outer == o.max_outer - 1) break;  // no sweep left to apply another correction
-    if (outer > 0 && (s = apply<double>(P, dptr(P, R_PROJ), nl, XF_C0, OP_GAMMA, XI_PROJ, FIN_PROJ)) != FFTH_OK)
-      return s;
+    if (outer > 0) {
+      if ((s = apply<float>(P, dptr(P, R_PROJ), nl, XF_C0, OP_GAMMA, XI_PROJ, FIN_PROJ)) != FFTH_OK) return s;
+      if ((s = read_states(P)) != FFTH_OK) return s;   // FIN_PROJ activated the inner states
+    }
     const Desc* di = dptr(P, R_INNER);
     for (int l = 0; l < nl; ++l) {
       const size_t bytes = (size_t)P->nvox * 6 * sizeof(float);
@@ -600,8 +602,8 @@ void ffth_default_opts(ffth_opts* o) {
   o->precision = FFTH_MIXED;
   o->tol = 1e-8;
   o->max_iter = 20000;
-  o->inner_tol = 1e-4;
-  o->max_outer = 12;
+  o->inner_tol = 1e-2;
+  o->max_outer = 30;
   o->check_every = 8;
 }
 

@@ -162,11 +162,11 @@ __global__ __launch_bounds__(NT) void k_xfwd(const Desc* __restrict__ descs, int
         apply_mat<T, ISO>(mat, ph, false, p, cp);
         acc0 += (double)frob_w(p, cp);
       } else if (mode == XF_C0) {
-        // tau = C0 : v (projection onto compatible fields: -Gamma0 * C0 v)
-        const T* vp = (const T*)d.r;
+        // tau = C0 : r for the projection -Gamma0 * C0 r (r is the FP64 residual)
+        const double* vp = (const double*)d.r;
         T v[6];
 #pragma unroll
-        for (int c = 0; c < 6; ++c) v[c] = vp[c * nvox + vox];
+        for (int c = 0; c < 6; ++c) v[c] = (T)vp[c * nvox + vox];
         const T tr = (T)lam0 * (v[0] + v[1] + v[2]);
 #pragma unroll
         for (int c = 0; c < 6; ++c) tau[c] = T(2) * (T)mu0 * v[c] + (c < 3 ? tr : T(0));
@@ -198,7 +198,7 @@ __global__ __launch_bounds__(NT) void k_xfwd(const Desc* __restrict__ descs, int
     spec[row * (H * 6) + rem] = o;
   }
   double sums[1] = {acc0};
-  block_sums<1, NT>(sums, d.part_f + (long)blockIdx.x * NRED);
+  block_sums<1, NT>(sums, d.part_f + blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -298,15 +298,16 @@ __global__ __launch_bounds__(NT) void k_xinv(const Desc* __restrict__ descs, int
     } else if (mode == XI_PROJ) {
       // eta = -P r.  Compatible part r_c = -eta goes to the FP32 inner right-hand
       // side; the rest, r - r_c = -(incompatible part of x), is applied to x.
-      T* xp = (T*)d.x;
-      const T* rp = (const T*)d.r;
+      // x and r are FP64 in every instantiation (the projection itself may run
+      // in FP32: it needs accuracy relative to r only).
+      double* xp = (double*)d.x;
+      const double* rp = (const double*)d.r;
       float* op = (float*)d.out;
       double rc[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         rc[c] = -(double)eta[c];
-        const T rv = rp[c * nvox + vox];
-        xp[c * nvox + vox] += rv - (T)rc[c];
+        xp[c * nvox + vox] += rp[c * nvox + vox] - rc[c];
         op[c * nvox + vox] = (float)rc[c];
       }
       acc0 += rc[0] * rc[0] + rc[1] * rc[1] + rc[2] * rc[2] + 2.0 * (rc[3] * rc[3] + rc[4] * rc[4] + rc[5] * rc[5]);
@@ -330,7 +331,7 @@ __global__ __launch_bounds__(NT) void k_xinv(const Desc* __restrict__ descs, int
     }
   }
   double sums[2] = {acc0, acc1};
-  block_sums<2, NT>(sums, d.part_i + (long)blockIdx.x * NRED);
+  block_sums<2, NT>(sums, d.part_i + blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -499,8 +500,9 @@ __global__ __launch_bounds__(NT) void k_zpass(const Desc* __restrict__ descs, in
 // Finalize: fixed-order sum of the block partials of one batch entry, then
 // the scalar update of its iteration state.  One block per entry.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_finalize(const Desc* __restrict__ descs, int op, int nblk_f, int nblk_i,
-                                                 double lam0, double mu0);
+constexpr int NT_FIN = 1024;
+__global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ descs, int op, int nblk_f, int nblk_i,
+                                                     double lam0, double mu0);
 
 // Volume averages of sigma = P_rhs + C:x (or C:(E + x)): 6 sums per block.
 template <bool ISO>

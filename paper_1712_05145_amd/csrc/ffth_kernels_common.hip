@@ -17,23 +17,44 @@ __device__ static void fin_check(SolverState* st) {
   }
 }
 
-__global__ __launch_bounds__(NT) void k_finalize(const Desc* __restrict__ descs, int op, int nblk_f, int nblk_i,
-                                                 double lam0, double mu0) {
+// Partial sums are slot-major: part[k * nblk + block].  Each op names how
+// many slots of each array it reads.
+__device__ static void fin_slots(int op, int& nf, int& ni) {
+  nf = 0;
+  ni = 0;
+  switch (op) {
+    case FIN_LS_FIRST: nf = 1; ni = 1; break;
+    case FIN_BS: ni = 1; break;
+    case FIN_RESID_INIT: ni = 2; break;
+    case FIN_CG_ALPHA: nf = 1; break;
+    case FIN_CG_BETA: ni = 2; break;
+    case FIN_OUTER: case FIN_OUTER_P: nf = 1; ni = 2; break;
+    case FIN_PROJ: ni = 2; break;
+    case FIN_SUMS_I: case FIN_O1RHS: ni = NRED; break;
+  }
+}
+
+__global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ descs, int op, int nblk_f, int nblk_i,
+                                                     double lam0, double mu0) {
   const Desc& d = descs[blockIdx.x];
   SolverState* st = d.st;
   if (!st->active) return;
   __shared__ double sf[NRED], si[NRED];
+  int nf, ni;
+  fin_slots(op, nf, ni);
   double af[NRED], ai[NRED];
 #pragma unroll
   for (int k = 0; k < NRED; ++k) {
     double a = 0.0, b = 0.0;
-    for (int i = threadIdx.x; i < nblk_f; i += NT) a += d.part_f[(long)i * NRED + k];
-    for (int i = threadIdx.x; i < nblk_i; i += NT) b += d.part_i[(long)i * NRED + k];
+    if (k < nf)
+      for (int i = threadIdx.x; i < nblk_f; i += NT_FIN) a += d.part_f[(long)k * nblk_f + i];
+    if (k < ni)
+      for (int i = threadIdx.x; i < nblk_i; i += NT_FIN) b += d.part_i[(long)k * nblk_i + i];
     af[k] = a;
     ai[k] = b;
   }
-  block_sums<NRED, NT>(af, sf);
-  block_sums<NRED, NT>(ai, si);
+  block_sums<NRED, NT_FIN>(af, sf);
+  block_sums<NRED, NT_FIN>(ai, si);
   __syncthreads();
   if (threadIdx.x != 0) return;
   const double amu = fabs(mu0);
@@ -86,17 +107,16 @@ __global__ __launch_bounds__(NT) void k_finalize(const Desc* __restrict__ descs,
       fin_check(st);
       break;
     case FIN_PROJ: {
-      // compatible residual projected: set up the FP32 inner solve
+      // compatible part of the FP64 residual: restart the FP32 inner solve on it
       SolverState* in = d.st2;
       st->fp64_apps++;
-      in->active = 1;
+      in->active = si[0] > 0.0 ? 1 : 0;
       in->nb2 = si[0];
       in->rr = si[1];
       in->first = 1;
       in->iters = 0;
       in->flag = FLAG_RUNNING;
       in->res = 1.0;
-      if (!(si[0] > 0.0)) in->active = 0;
       break;
     }
     case FIN_OUTER:
@@ -169,7 +189,7 @@ __global__ __launch_bounds__(NT) void k_mean_stress(const Desc* __restrict__ des
 #pragma unroll
     for (int c = 0; c < 6; ++c) acc[c] += s[c];
   }
-  block_sums<NRED, NT>(acc, d.part_i + (long)blockIdx.x * NRED);
+  block_sums<NRED, NT>(acc, d.part_i + blockIdx.x, gridDim.x);
 }
 
 template <bool ISO>
@@ -219,7 +239,7 @@ __global__ __launch_bounds__(NT) void k_order1_point(const Desc* __restrict__ de
     acc[3] += g[1];
     acc[4] += g[2];
   }
-  block_sums<NRED, NT>(acc, d.part_i + (long)blockIdx.x * NRED);
+  block_sums<NRED, NT>(acc, d.part_i + blockIdx.x, gridDim.x);
 }
 
 __global__ void k_widen(const Desc* __restrict__ descs, long n) {
@@ -257,7 +277,7 @@ bool size_supported(int n) {
 
 hipError_t launch_finalize(int nbatch, hipStream_t s, const Desc* d, int op, int nblk_f, int nblk_i, double lam0,
                            double mu0) {
-  hipLaunchKernelGGL(k_finalize, dim3(nbatch), dim3(NT), 0, s, d, op, nblk_f, nblk_i, lam0, mu0);
+  hipLaunchKernelGGL(k_finalize, dim3(nbatch), dim3(NT_FIN), 0, s, d, op, nblk_f, nblk_i, lam0, mu0);
   return hipGetLastError();
 }
 

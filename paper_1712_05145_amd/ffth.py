@@ -119,7 +119,7 @@ def _darr(a):
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def make_opts(scheme="cg", precision="mixed", tol=1e-8, max_iter=20000, inner_tol=1e-4, max_outer=12,
+def make_opts(scheme="cg", precision="mixed", tol=1e-8, max_iter=20000, inner_tol=1e-2, max_outer=30,
               check_every=8):
     o = ffth_opts()
     load().ffth_default_opts(ctypes.byref(o))
@@ -204,7 +204,7 @@ class Solver:
     """
 
     def __init__(self, phase, lam0, mu0, lame=None, voigt21=None, nloads=1, order=0, scheme="cg",
-                 precision="mixed", tol=1e-8, max_iter=20000, inner_tol=1e-4, max_outer=12, check_every=8,
+                 precision="mixed", tol=1e-8, max_iter=20000, inner_tol=1e-2, max_outer=30, check_every=8,
                  device="cuda:0", stream=None):
         import torch
         self.torch = torch

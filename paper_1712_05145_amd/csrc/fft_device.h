@@ -175,33 +175,62 @@ template <typename T, int N, int NT> __device__ __forceinline__ void build_twidd
 // ---------------------------------------------------------------------------
 template <bool PADDED> __device__ __forceinline__ int padx(int e) { return PADDED ? e + (e >> 4) : e; }
 
-template <typename T, int N, int S, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR>
+// Two adjacent complex values moved with one 16-byte access (FP32 layouts in
+// which consecutive sequences are adjacent in memory).
+template <typename T> struct alignas(16) Pair { C2<T> a, b; };
+
+template <typename T, int V> __device__ __forceinline__ void load_v(const C2<T>* p, C2<T> (&o)[V]) {
+  if constexpr (V == 2) {
+    const Pair<T> q = *reinterpret_cast<const Pair<T>*>(p);
+    o[0] = q.a;
+    o[1] = q.b;
+  } else {
+    o[0] = p[0];
+  }
+}
+template <typename T, int V> __device__ __forceinline__ void store_v(C2<T>* p, const C2<T> (&o)[V]) {
+  if constexpr (V == 2) {
+    *reinterpret_cast<Pair<T>*>(p) = Pair<T>{o[0], o[1]};
+  } else {
+    p[0] = o[0];
+  }
+}
+
+// One Stockham stage.  Work items are (group of V adjacent sequences, butterfly).
+// V = 2 requires FFAST layouts with sequence stride FS = 1 (adjacent sequences).
+template <typename T, int N, int S, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR, int V>
 __device__ __forceinline__ void fft_stage(C2<T>* buf, const C2<T>* tw) {
+  static_assert(V == 1 || (FFAST && FS == 1 && NFFT % V == 0 && ES % V == 0), "vector width needs adjacent sequences");
   constexpr int R = fac_radix(N, S);
   constexpr int NS = fac_prefix(N, S);
   constexpr int NB = N / R;
-  constexpr int ITEMS = NFFT * NB;
+  constexpr int NG = NFFT / V;
+  constexpr int ITEMS = NG * NB;
   constexpr int K = (ITEMS + NT - 1) / NT;
-  C2<T> v[K][R];
+  C2<T> v[K][V][R];
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     const int it = threadIdx.x + k * NT;
     if ((ITEMS % NT == 0) || it < ITEMS) {
-      const int f = FFAST ? it % NFFT : it / NB;
-      const int j = FFAST ? it / NFFT : it % NB;
-      const C2<T>* src = buf + f * FS;
+      const int g = FFAST ? it % NG : it / NB;
+      const int j = FFAST ? it / NG : it % NB;
+      const C2<T>* src = buf + g * V * FS;
       const int kk = j % NS;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        C2<T> a = src[padx<PADDED>((j + r * NB) * ES)];
+        C2<T> a[V];
+        load_v<T, V>(src + padx<PADDED>((j + r * NB) * ES), a);
         if (NS > 1 && r > 0) {
           C2<T> w = tw[r * kk * (N / (NS * R))];
           if (DIR > 0) w.y = -w.y;
-          a = cmul(a, w);
+#pragma unroll
+          for (int q = 0; q < V; ++q) a[q] = cmul(a[q], w);
         }
-        v[k][r] = a;
+#pragma unroll
+        for (int q = 0; q < V; ++q) v[k][q][r] = a[q];
       }
-      dft<R, DIR>(v[k]);
+#pragma unroll
+      for (int q = 0; q < V; ++q) dft<R, DIR>(v[k][q]);
     }
   }
   __syncthreads();
@@ -209,30 +238,35 @@ __device__ __forceinline__ void fft_stage(C2<T>* buf, const C2<T>* tw) {
   for (int k = 0; k < K; ++k) {
     const int it = threadIdx.x + k * NT;
     if ((ITEMS % NT == 0) || it < ITEMS) {
-      const int f = FFAST ? it % NFFT : it / NB;
-      const int j = FFAST ? it / NFFT : it % NB;
-      C2<T>* dst = buf + f * FS;
+      const int g = FFAST ? it % NG : it / NB;
+      const int j = FFAST ? it / NG : it % NB;
+      C2<T>* dst = buf + g * V * FS;
       const int base = (j / NS) * NS * R + (j % NS);
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[padx<PADDED>((base + r * NS) * ES)] = v[k][r];
+      for (int r = 0; r < R; ++r) {
+        C2<T> a[V];
+#pragma unroll
+        for (int q = 0; q < V; ++q) a[q] = v[k][q][r];
+        store_v<T, V>(dst + padx<PADDED>((base + r * NS) * ES), a);
+      }
     }
   }
   __syncthreads();
 }
 
-template <typename T, int N, int S, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR>
+template <typename T, int N, int S, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR, int V>
 __device__ __forceinline__ void fft_stages(C2<T>* buf, const C2<T>* tw) {
   if constexpr (S < fac_count(N)) {
-    fft_stage<T, N, S, NFFT, NT, ES, FS, FFAST, PADDED, DIR>(buf, tw);
-    fft_stages<T, N, S + 1, NFFT, NT, ES, FS, FFAST, PADDED, DIR>(buf, tw);
+    fft_stage<T, N, S, NFFT, NT, ES, FS, FFAST, PADDED, DIR, V>(buf, tw);
+    fft_stages<T, N, S + 1, NFFT, NT, ES, FS, FFAST, PADDED, DIR, V>(buf, tw);
   }
 }
 
 // Caller must __syncthreads() before (data written) - the stages end with a barrier.
-template <typename T, int N, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR>
+template <typename T, int N, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR, int V = 1>
 __device__ __forceinline__ void lds_fft(C2<T>* buf, const C2<T>* tw) {
   static_assert(fac_count(N) > 0, "unsupported FFT length");
-  fft_stages<T, N, 0, NFFT, NT, ES, FS, FFAST, PADDED, DIR>(buf, tw);
+  fft_stages<T, N, 0, NFFT, NT, ES, FS, FFAST, PADDED, DIR, V>(buf, tw);
 }
 
 // ---------------------------------------------------------------------------

@@ -51,9 +51,10 @@ struct Layout {
   int ndesc, nstate, nblk;
 };
 
-int x_blocks(int n0, int n1, int n2, bool dbl) {
+int x_blocks(int n0, int n1, int n2, bool dbl, bool inverse) {
   const long rows = (long)n0 * n1;
-  const int r = dbl ? Launch<double>::x_rows(n2) : Launch<float>::x_rows(n2);
+  const int r = inverse ? (dbl ? Launch<double>::xi_rows(n2) : Launch<float>::xi_rows(n2))
+                        : (dbl ? Launch<double>::x_rows(n2) : Launch<float>::x_rows(n2));
   return r > 0 ? (int)((rows + r - 1) / r) : 0;
 }
 
@@ -65,7 +66,9 @@ Layout make_layout(const int n[3], int nph, int nloads, int order, const ffth_op
   const int prec = o.precision, scheme = o.scheme;
   L.ndesc = 7 * nloads + 8;
   L.nstate = 3 * nloads + 1;
-  L.nblk = std::max({x_blocks(n[0], n[1], n[2], true), x_blocks(n[0], n[1], n[2], false), ms_blocks(nvox)});
+  L.nblk = std::max({x_blocks(n[0], n[1], n[2], true, false), x_blocks(n[0], n[1], n[2], false, false),
+                     x_blocks(n[0], n[1], n[2], true, true), x_blocks(n[0], n[1], n[2], false, true),
+                     ms_blocks(nvox)});
   // per-load FP32 / FP64 field counts
   if (prec == FFTH_FP32) L.nf32 = scheme == FFTH_CG ? 3 : 1;
   if (prec == FFTH_MIXED) L.nf32 = scheme == FFTH_CG ? 3 : 2;
@@ -144,7 +147,8 @@ struct ffth_plan {
   Desc* d_desc;
   SolverState* d_state;
   SolverState* h_state;   // pinned host mirror (read-back)
-  int nx64, nx32;         // x-pass blocks per precision
+  int nx64, nx32;         // forward x-pass blocks per precision
+  int ni64, ni32;         // inverse x-pass blocks per precision
   std::vector<Desc> h_desc;
   // kernel timing (diagnostics): events bracket every launch when enabled
   bool prof = false;
@@ -283,6 +287,7 @@ ffth_status read_states(ffth_plan* P) {
 // ---- pass launchers -------------------------------------------------------
 
 template <typename T> int xblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->nx64 : P->nx32; }
+template <typename T> int iblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->ni64 : P->ni32; }
 
 template <typename T> ffth_status xfwd(ffth_plan* P, const Desc* d, int nb, int mode) {
   ProfScope ps(P, sizeof(T) == 8 ? C_XF64 : C_XF32);
@@ -317,7 +322,7 @@ template <typename T> ffth_status yzy(ffth_plan* P, const Desc* d, int nb, int o
 
 template <typename T> ffth_status xinv(ffth_plan* P, const Desc* d, int nb, int mode) {
   ProfScope ps(P, sizeof(T) == 8 ? C_XI64 : C_XI32);
-  HIPCHK(Launch<T>::xinv(P->n[2], P->iso, dim3(xblocks<T>(P), nb), P->stream, d, mode, P->rows, P->nvox, P->lam0,
+  HIPCHK(Launch<T>::xinv(P->n[2], P->iso, dim3(iblocks<T>(P), nb), P->stream, d, mode, P->rows, P->nvox, P->lam0,
                          P->mu0));
   return FFTH_OK;
 }
@@ -336,7 +341,7 @@ ffth_status apply(ffth_plan* P, const Desc* d, int nb, int xf, int spec_op, int 
   if (xf == XF_CG && (s = fin(P, d, nb, FIN_CG_ALPHA, xblocks<T>(P), 0)) != FFTH_OK) return s;
   if ((s = yzy<T>(P, d, nb, spec_op)) != FFTH_OK) return s;
   if ((s = xinv<T>(P, d, nb, xi)) != FFTH_OK) return s;
-  if (fin_op >= 0 && (s = fin(P, d, nb, fin_op, xblocks<T>(P), xblocks<T>(P))) != FFTH_OK) return s;
+  if (fin_op >= 0 && (s = fin(P, d, nb, fin_op, xblocks<T>(P), iblocks<T>(P))) != FFTH_OK) return s;
   return FFTH_OK;
 }
 
@@ -694,8 +699,10 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
   P->mat32 = (float*)(P->ws + L.mat32);
   P->d_desc = (Desc*)(P->ws + L.desc);
   P->d_state = (SolverState*)(P->ws + L.state);
-  P->nx64 = x_blocks(p->n[0], p->n[1], p->n[2], true);
-  P->nx32 = x_blocks(p->n[0], p->n[1], p->n[2], false);
+  P->nx64 = x_blocks(p->n[0], p->n[1], p->n[2], true, false);
+  P->nx32 = x_blocks(p->n[0], p->n[1], p->n[2], false, false);
+  P->ni64 = x_blocks(p->n[0], p->n[1], p->n[2], true, true);
+  P->ni32 = x_blocks(p->n[0], p->n[1], p->n[2], false, true);
   P->h_desc.assign(L.ndesc, Desc{});
   if (!hip_ok(hipHostMalloc((void**)&P->h_state, L.nstate * sizeof(SolverState), hipHostMallocDefault),
               "hipHostMalloc")) {

@@ -29,8 +29,14 @@ constexpr int pow2_floor(int v) {
   while (p * 2 <= v) p *= 2;
   return p;
 }
-template <typename T> constexpr int x_rows(int n) {
-  int r = (sizeof(T) == 4 ? 1024 : 512) / n;
+// Tile shapes and block sizes, chosen from a sweep of every pass at 256^3 on
+// MI355X (rows per x-pass block, interleaved columns per y/z block, threads).
+template <typename T> constexpr int x_rows(int n) {          // forward x-pass
+  int r = 512 / n;
+  return r < 1 ? 1 : pow2_floor(r);
+}
+template <typename T> constexpr int xi_rows(int n) {         // inverse x-pass
+  int r = (sizeof(T) == 4 ? 256 : 512) / n;
   return r < 1 ? 1 : pow2_floor(r);
 }
 template <typename T> constexpr int y_cols(int n) {
@@ -39,11 +45,15 @@ template <typename T> constexpr int y_cols(int n) {
   c = c > cap ? cap : c;
   return c < 1 ? 1 : pow2_floor(c);
 }
+template <typename T> constexpr int y_threads(int n) { return sizeof(T) == 4 && n >= 128 ? 512 : 256; }
 template <typename T> constexpr int z_cols(int n) {
-  int c = (sizeof(T) == 4 ? 1024 : 512) / n;
+  int c = 256 / n;
   c = c > 16 ? 16 : c;
   return c < 1 ? 1 : pow2_floor(c);
 }
+// vector width of LDS / global accesses in the y and z passes (1: measured
+// faster than 16-byte pairs, which halve the threads busy in each stage)
+template <typename T> constexpr int vec_width() { return 1; }
 
 // ---------------------------------------------------------------------------
 // Constitutive law helpers.  Tensor-component vectors (11,22,33,23,13,12).
@@ -88,24 +98,34 @@ __device__ __forceinline__ double c0_ip(double lam0, double mu0, const double (&
 // ---------------------------------------------------------------------------
 // x-pass, forward: polarization + real-to-complex FFT along axis 2.
 // ---------------------------------------------------------------------------
-template <typename T, int N2, bool ISO>
-__global__ __launch_bounds__(NT) void k_xfwd(const Desc* __restrict__ descs, int mode, long rows_total,
-                                             long nvox, double lam0, double mu0) {
-  constexpr int ROWS = x_rows<T>(N2);
+// MI355X dispatches the blocks of a grid round-robin over its 8 XCDs (each
+// with its own L2).  Renumbering so that each XCD walks a contiguous range of
+// tiles keeps neighbouring tiles, which share cache lines at tile edges, in
+// the same L2 at about the same time.
+__device__ __forceinline__ int xcd_tile(int bid, int nblk) {
+  constexpr int NX = 8;
+  const int q = nblk / NX, r = nblk % NX;
+  const int x = bid % NX, i = bid / NX;
+  return x * q + (x < r ? x : r) + i;
+}
+
+template <typename T, int N2, bool ISO, int ROWS = x_rows<T>(N2), int NTB = NT>
+__global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, int mode, long rows_total,
+                                              long nvox, double lam0, double mu0) {
   constexpr int RS = N2 + N2 / 16;
   constexpr int H = N2 / 2;
   __shared__ C2<T> z[ROWS * 3 * RS];
   __shared__ C2<T> tw[N2];
   const Desc& d = descs[blockIdx.y];
   if (!d.st->active) return;
-  build_twiddles<T, N2, NT>(tw);
+  build_twiddles<T, N2, NTB>(tw);
   const long row0 = (long)blockIdx.x * ROWS;
   const T* mat = mat_of<T>(d);
   double acc0 = 0.0;
   const T beta = (T)d.st->beta;
   const bool first = d.st->first != 0;
 
-  for (int v = threadIdx.x; v < ROWS * N2; v += NT) {
+  for (int v = threadIdx.x; v < ROWS * N2; v += NTB) {
     const int rr = v / N2, i2 = v % N2;
     const long row = row0 + rr;
     T tau[6] = {0, 0, 0, 0, 0, 0};
@@ -181,10 +201,10 @@ __global__ __launch_bounds__(NT) void k_xfwd(const Desc* __restrict__ descs, int
     for (int q = 0; q < 3; ++q) z[(rr * 3 + q) * RS + padx<true>(i2)] = C2<T>{tau[2 * q], tau[2 * q + 1]};
   }
   __syncthreads();
-  lds_fft<T, N2, ROWS * 3, NT, 1, RS, false, true, -1>(z, tw);
+  lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, -1>(z, tw);
 
   C2<T>* spec = (C2<T>*)d.spec;
-  for (int v = threadIdx.x; v < ROWS * H * 6; v += NT) {
+  for (int v = threadIdx.x; v < ROWS * H * 6; v += NTB) {
     const int rr = v / (H * 6), rem = v % (H * 6);
     const long row = row0 + rr;
     if (row >= rows_total) continue;
@@ -198,27 +218,26 @@ __global__ __launch_bounds__(NT) void k_xfwd(const Desc* __restrict__ descs, int
     spec[row * (H * 6) + rem] = o;
   }
   double sums[1] = {acc0};
-  block_sums<1, NT>(sums, d.part_f + blockIdx.x, gridDim.x);
+  block_sums<1, NTB>(sums, d.part_f + blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
 // x-pass, inverse: complex-to-real FFT along axis 2 + update + reductions.
 // ---------------------------------------------------------------------------
-template <typename T, int N2, bool ISO>
-__global__ __launch_bounds__(NT) void k_xinv(const Desc* __restrict__ descs, int mode, long rows_total, long nvox,
-                                             double lam0, double mu0) {
-  constexpr int ROWS = x_rows<T>(N2);
+template <typename T, int N2, bool ISO, int ROWS = xi_rows<T>(N2), int NTB = NT>
+__global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, int mode, long rows_total, long nvox,
+                                              double lam0, double mu0) {
   constexpr int RS = N2 + N2 / 16;
   constexpr int H = N2 / 2;
   __shared__ C2<T> z[ROWS * 3 * RS];
   __shared__ C2<T> tw[N2];
   const Desc& d = descs[blockIdx.y];
   if (!d.st->active) return;
-  build_twiddles<T, N2, NT>(tw);
+  build_twiddles<T, N2, NTB>(tw);
   const long row0 = (long)blockIdx.x * ROWS;
   const C2<T>* spec = (const C2<T>*)d.spec;
 
-  for (int v = threadIdx.x; v < ROWS * H * 3; v += NT) {
+  for (int v = threadIdx.x; v < ROWS * H * 3; v += NTB) {
     const int rr = v / (H * 3), rem = v % (H * 3);
     const int k = rem / 3, q = rem % 3;
     const long row = row0 + rr;
@@ -238,11 +257,11 @@ __global__ __launch_bounds__(NT) void k_xinv(const Desc* __restrict__ descs, int
     }
   }
   __syncthreads();
-  lds_fft<T, N2, ROWS * 3, NT, 1, RS, false, true, +1>(z, tw);
+  lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, +1>(z, tw);
 
   const T alpha = (T)d.st->alpha;
   double acc0 = 0.0, acc1 = 0.0;
-  for (int v = threadIdx.x; v < ROWS * N2; v += NT) {
+  for (int v = threadIdx.x; v < ROWS * N2; v += NTB) {
     const int rr = v / N2, i2 = v % N2;
     const long row = row0 + rr;
     if (row >= rows_total) continue;
@@ -331,41 +350,54 @@ __global__ __launch_bounds__(NT) void k_xinv(const Desc* __restrict__ descs, int
     }
   }
   double sums[2] = {acc0, acc1};
-  block_sums<2, NT>(sums, d.part_i + blockIdx.x, gridDim.x);
+  block_sums<2, NTB>(sums, d.part_i + blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
 // y-pass: complex FFT along axis 1, in place.  Block = one i0 plane, CW
 // consecutive columns of the [n1][n2/2 * 6] plane.
 // ---------------------------------------------------------------------------
-template <typename T, int N1, int DIR>
+// ncols is a multiple of 6 (and of V), so a V-group of columns is either all
+// inside or all outside the plane.
+template <typename T, int N1, int CW, int NTB, int DIR, int V>
 __device__ __forceinline__ void ypass_body(C2<T>* base, int ncols, int c0, C2<T>* buf, const C2<T>* tw) {
-  constexpr int CW = y_cols<T>(N1);
-  for (int v = threadIdx.x; v < N1 * CW; v += NT) {
-    const int i1 = v / CW, col = v % CW;
-    buf[v] = (c0 + col < ncols) ? base[(long)i1 * ncols + col] : C2<T>{0, 0};
+  for (int v = threadIdx.x; v < N1 * CW / V; v += NTB) {
+    const int i1 = v / (CW / V), col = (v % (CW / V)) * V;
+    C2<T> a[V];
+    if (c0 + col < ncols) {
+      load_v<T, V>(base + (long)i1 * ncols + col, a);
+    } else {
+#pragma unroll
+      for (int q = 0; q < V; ++q) a[q] = C2<T>{0, 0};
+    }
+    store_v<T, V>(buf + i1 * CW + col, a);
   }
   __syncthreads();
-  lds_fft<T, N1, CW, NT, CW, 1, true, false, DIR>(buf, tw);
-  for (int v = threadIdx.x; v < N1 * CW; v += NT) {
-    const int i1 = v / CW, col = v % CW;
-    if (c0 + col < ncols) base[(long)i1 * ncols + col] = buf[v];
+  lds_fft<T, N1, CW, NTB, CW, 1, true, false, DIR, V>(buf, tw);
+  for (int v = threadIdx.x; v < N1 * CW / V; v += NTB) {
+    const int i1 = v / (CW / V), col = (v % (CW / V)) * V;
+    if (c0 + col < ncols) {
+      C2<T> a[V];
+      load_v<T, V>(buf + i1 * CW + col, a);
+      store_v<T, V>(base + (long)i1 * ncols + col, a);
+    }
   }
 }
 
-template <typename T, int N1>
-__global__ __launch_bounds__(NT) void k_ypass(const Desc* __restrict__ descs, int dir, int ncols, int ntiles) {
-  constexpr int CW = y_cols<T>(N1);
-  __shared__ C2<T> buf[N1 * CW];
+template <typename T, int N1, int CW = y_cols<T>(N1), int NTB = y_threads<T>(N1), bool REMAP = true,
+          int V = vec_width<T>()>
+__global__ __launch_bounds__(NTB) void k_ypass(const Desc* __restrict__ descs, int dir, int ncols, int ntiles) {
+  __shared__ __attribute__((aligned(16))) C2<T> buf[N1 * CW];
   __shared__ C2<T> tw[N1];
   const Desc& d = descs[blockIdx.y];
   if (!d.st->active) return;
-  build_twiddles<T, N1, NT>(tw);
-  const long i0 = blockIdx.x / ntiles;
-  const int c0 = (blockIdx.x % ntiles) * CW;
+  build_twiddles<T, N1, NTB>(tw);
+  const int bid = REMAP ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const long i0 = bid / ntiles;
+  const int c0 = (bid % ntiles) * CW;
   C2<T>* base = (C2<T>*)d.spec + i0 * N1 * (long)ncols + c0;
-  if (dir < 0) ypass_body<T, N1, -1>(base, ncols, c0, buf, tw);
-  else ypass_body<T, N1, +1>(base, ncols, c0, buf, tw);
+  if (dir < 0) ypass_body<T, N1, CW, NTB, -1, V>(base, ncols, c0, buf, tw);
+  else ypass_body<T, N1, CW, NTB, +1, V>(base, ncols, c0, buf, tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -439,32 +471,32 @@ __device__ __forceinline__ void spectral_op(int op, T (&in)[6][2], T (&out)[6][2
   }
 }
 
-template <typename T, int N0, int DIR>
-__device__ __forceinline__ void zfft(C2<T>* buf, const C2<T>* tw) {
-  constexpr int W = z_cols<T>(N0) * 6;
-  lds_fft<T, N0, W, NT, W, 1, true, false, DIR>(buf, tw);
-}
-
-template <typename T, int N0>
-__global__ __launch_bounds__(NT) void k_zpass(const Desc* __restrict__ descs, int op, int n1, int h, double lam0,
-                                              double mu0, double scale) {
-  constexpr int TK = z_cols<T>(N0);
+template <typename T, int N0, int TK = z_cols<T>(N0), int NTB = NT, bool REMAP = true, int V = vec_width<T>()>
+__global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, int op, int n1, int h, double lam0,
+                                               double mu0, double scale) {
   constexpr int W = TK * 6;
-  __shared__ C2<T> buf[N0 * W];
+  __shared__ __attribute__((aligned(16))) C2<T> buf[N0 * W];
   __shared__ C2<T> tw[N0];
   const Desc& d = descs[blockIdx.y];
   if (!d.st->active) return;
-  build_twiddles<T, N0, NT>(tw);
+  build_twiddles<T, N0, NTB>(tw);
   const long M = (long)n1 * h;
-  const long m0 = (long)blockIdx.x * TK;
+  const long m0 = (long)(REMAP ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x) * TK;
   C2<T>* spec = (C2<T>*)d.spec;
-  for (int v = threadIdx.x; v < N0 * W; v += NT) {
-    const int i0 = v / W, w = v % W;
-    buf[v] = (m0 + w / 6 < M) ? spec[((long)i0 * M + m0) * 6 + w] : C2<T>{0, 0};
+  for (int v = threadIdx.x; v < N0 * W / V; v += NTB) {
+    const int i0 = v / (W / V), w = (v % (W / V)) * V;
+    C2<T> a[V];
+    if (m0 + w / 6 < M) {
+      load_v<T, V>(spec + ((long)i0 * M + m0) * 6 + w, a);
+    } else {
+#pragma unroll
+      for (int q = 0; q < V; ++q) a[q] = C2<T>{0, 0};
+    }
+    store_v<T, V>(buf + i0 * W + w, a);
   }
   __syncthreads();
-  zfft<T, N0, -1>(buf, tw);
-  for (int v = threadIdx.x; v < N0 * TK; v += NT) {
+  lds_fft<T, N0, W, NTB, W, 1, true, false, -1, V>(buf, tw);
+  for (int v = threadIdx.x; v < N0 * TK; v += NTB) {
     const int k0 = v / TK, col = v % TK;
     const long m = m0 + col;
     if (m >= M) continue;
@@ -475,9 +507,14 @@ __global__ __launch_bounds__(NT) void k_zpass(const Desc* __restrict__ descs, in
     C2<T>* e = buf + k0 * W + col * 6;
     T in[6][2], out[6][2];
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      in[c][0] = e[c].x;
-      in[c][1] = e[c].y;
+    for (int c = 0; c < 6; c += V) {
+      C2<T> a[V];
+      load_v<T, V>(e + c, a);
+#pragma unroll
+      for (int q = 0; q < V; ++q) {
+        in[c + q][0] = a[q].x;
+        in[c + q][1] = a[q].y;
+      }
     }
     if (nyq || (k0s == 0 && k1s == 0 && k2 == 0)) {
 #pragma unroll
@@ -486,13 +523,22 @@ __global__ __launch_bounds__(NT) void k_zpass(const Desc* __restrict__ descs, in
       spectral_op<T>(op, in, out, (T)k0s, (T)k1s, (T)k2, lam0, mu0, (T)scale);
     }
 #pragma unroll
-    for (int c = 0; c < 6; ++c) e[c] = C2<T>{out[c][0], out[c][1]};
+    for (int c = 0; c < 6; c += V) {
+      C2<T> a[V];
+#pragma unroll
+      for (int q = 0; q < V; ++q) a[q] = C2<T>{out[c + q][0], out[c + q][1]};
+      store_v<T, V>(e + c, a);
+    }
   }
   __syncthreads();
-  zfft<T, N0, +1>(buf, tw);
-  for (int v = threadIdx.x; v < N0 * W; v += NT) {
-    const int i0 = v / W, w = v % W;
-    if (m0 + w / 6 < M) spec[((long)i0 * M + m0) * 6 + w] = buf[v];
+  lds_fft<T, N0, W, NTB, W, 1, true, false, +1, V>(buf, tw);
+  for (int v = threadIdx.x; v < N0 * W / V; v += NTB) {
+    const int i0 = v / (W / V), w = (v % (W / V)) * V;
+    if (m0 + w / 6 < M) {
+      C2<T> a[V];
+      load_v<T, V>(buf + i0 * W + w, a);
+      store_v<T, V>(spec + ((long)i0 * M + m0) * 6 + w, a);
+    }
   }
 }
 

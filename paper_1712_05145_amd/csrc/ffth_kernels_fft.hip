@@ -18,6 +18,12 @@ template <typename T> int Launch<T>::x_rows(int n) {
 #undef FFTH_CASE
   return 0;
 }
+template <typename T> int Launch<T>::xi_rows(int n) {
+#define FFTH_CASE(N) if (n == N) return ffth::xi_rows<T>(N);
+  FFTH_SIZES(FFTH_CASE)
+#undef FFTH_CASE
+  return 0;
+}
 template <typename T> int Launch<T>::y_cols(int n) {
 #define FFTH_CASE(N) if (n == N) return ffth::y_cols<T>(N);
   FFTH_SIZES(FFTH_CASE)
@@ -59,10 +65,10 @@ template <typename T> hipError_t Launch<T>::xinv(int n2, bool iso, dim3 grid, hi
 
 template <typename T> hipError_t Launch<T>::ypass(int n1, dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols,
                                         int ntiles) {
-#define FFTH_CASE(N)                                                                      \
-  if (n1 == N) {                                                                          \
-    hipLaunchKernelGGL((k_ypass<T, N>), grid, dim3(NT), 0, s, d, dir, ncols, ntiles);     \
-    return hipGetLastError();                                                             \
+#define FFTH_CASE(N)                                                                                  \
+  if (n1 == N) {                                                                                      \
+    hipLaunchKernelGGL((k_ypass<T, N>), grid, dim3(ffth::y_threads<T>(N)), 0, s, d, dir, ncols, ntiles); \
+    return hipGetLastError();                                                                         \
   }
   FFTH_SIZES(FFTH_CASE)
 #undef FFTH_CASE

@@ -13,6 +13,7 @@ bool size_supported(int n);
 
 template <typename T> struct Launch {
   static int x_rows(int n);
+  static int xi_rows(int n);
   static int y_cols(int n);
   static int z_cols(int n);
   static hipError_t xfwd(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox,

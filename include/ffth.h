@@ -184,6 +184,37 @@ ffth_status ffth_profile_enable(ffth_plan *plan, int32_t on);
 ffth_status ffth_profile_read(ffth_plan *plan, int32_t category, int64_t *launches, double *ms);
 const char *ffth_profile_name(int32_t category);
 
+/* ---- Serving: continuous batching of order-0 solves ----------------------
+ * A server owns no device memory: the caller hands it one device arena (the
+ * HBM budget).  Requests (one RVE, 1..6 macro strains each, e.g. the six unit
+ * loads of an effective-stiffness request) are admitted in arrival order as
+ * soon as their memory (ffth_request_bytes) fits the free arena and one of
+ * max_running slots is free.  Each ffth_server_step advances every running
+ * request by one phase of the mixed-precision solve (an FP64 residual sweep,
+ * the compatible projection, or check_every FP32 iterations); requests of the
+ * same grid size share every kernel launch.  A completed request returns its
+ * memory to the arena and its results (mean stresses, i.e. C_eff columns
+ * for unit loads) to ffth_poll.  Results do not depend on what else runs:
+ * every load keeps its own iteration state and reductions are fixed-order.
+ *   arena: DEVICE, 256-byte aligned, caller-owned, outlives the server.
+ *   opts:  precision must be FFTH_MIXED.
+ *   problem->phase must stay valid until the request completes.
+ * Not thread-safe: drive a server from one host thread. */
+typedef struct ffth_server ffth_server;
+size_t ffth_request_bytes(const int32_t n[3], int32_t nphases, int32_t nloads, const ffth_opts *o);
+ffth_status ffth_server_create(ffth_server **out, void *arena, size_t arena_bytes, const ffth_opts *o,
+                               int32_t max_running, void *hip_stream);
+/* FFTH_ERR_OOM if the request can never fit the arena. */
+ffth_status ffth_submit(ffth_server *srv, const ffth_problem *p, int32_t nloads, const double *E,
+                        uint64_t *request_id);
+/* One round; running / waiting (may be NULL) receive the queue sizes after it. */
+ffth_status ffth_server_step(ffth_server *srv, int32_t *running, int32_t *waiting);
+/* FFTH_ERR_BUSY until complete; then the request's status, res[nloads] filled,
+ * and the id is released.  FFTH_ERR_CANCELLED for cancelled requests. */
+ffth_status ffth_poll(ffth_server *srv, uint64_t request_id, ffth_result *res);
+ffth_status ffth_cancel(ffth_server *srv, uint64_t request_id);
+ffth_status ffth_server_destroy(ffth_server *srv);
+
 const char *ffth_status_string(ffth_status s);
 
 /* Last HIP error text recorded by the library on this thread ("" if none). */

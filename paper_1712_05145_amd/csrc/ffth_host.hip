@@ -9,6 +9,9 @@
 
 #include <algorithm>
 #include <chrono>
+#include <deque>
+#include <tuple>
+#include <map>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -45,7 +48,7 @@ bool hip_ok(hipError_t e, const char* what) {
 // Workspace regions (byte offsets).  Computed identically for sizing and
 // for carving a caller's buffer.
 struct Layout {
-  size_t mat64, mat32, desc, state, part, spec, f32, f64, P, X1, g, misc, total;
+  size_t mat64, mat32, desc, cdesc, state, part, spec, f32, f64, P, X1, g, misc, total;
   size_t spec_stride, f32_stride, f64_stride, part_stride;
   int nf32, nf64;
   int ndesc, nstate, nblk;
@@ -82,6 +85,7 @@ Layout make_layout(const int n[3], int nph, int nloads, int order, const ffth_op
   L.mat64 = off; off += al((size_t)nph * 72 * sizeof(double));
   L.mat32 = off; off += al((size_t)nph * 72 * sizeof(float));
   L.desc = off; off += al((size_t)L.ndesc * sizeof(Desc));
+  L.cdesc = off; off += al((size_t)4 * nloads * sizeof(Desc));   // compacted active-load copies
   L.state = off; off += al((size_t)L.nstate * sizeof(SolverState));
   L.misc = off; off += ALIGN;
   L.part = off; off += (size_t)(2 * nloads + 2) * L.part_stride;
@@ -147,6 +151,8 @@ struct ffth_plan {
   Desc* d_desc;
   SolverState* d_state;
   SolverState* h_state;   // pinned host mirror (read-back)
+  Desc* d_cdesc;          // 4 regions of nloads compacted descriptors
+  Desc* h_cdesc;          // pinned staging for them
   int nx64, nx32;         // forward x-pass blocks per precision
   int ni64, ni32;         // inverse x-pass blocks per precision
   std::vector<Desc> h_desc;
@@ -245,6 +251,8 @@ Desc base_desc(ffth_plan* P, int l) {
   d.spec = spec_ptr(P, l);
   d.part_f = part_ptr(P, 2 * l);
   d.part_i = part_ptr(P, 2 * l + 1);
+  d.lam0 = P->lam0;
+  d.mu0 = P->mu0;
   d.nc = 6;
   return d;
 }
@@ -273,6 +281,7 @@ ffth_status upload_states(ffth_plan* P, const std::vector<SolverState>& s, int f
   HIPCHK(hipMemcpyAsync(P->d_state + first_slot, s.data(), s.size() * sizeof(SolverState), hipMemcpyHostToDevice,
                         P->stream));
   HIPCHK(hipStreamSynchronize(P->stream));
+  std::memcpy(P->h_state + first_slot, s.data(), s.size() * sizeof(SolverState));  // keep the mirror current
   return FFTH_OK;
 }
 
@@ -291,8 +300,7 @@ template <typename T> int iblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->ni6
 
 template <typename T> ffth_status xfwd(ffth_plan* P, const Desc* d, int nb, int mode) {
   ProfScope ps(P, sizeof(T) == 8 ? C_XF64 : C_XF32);
-  HIPCHK(Launch<T>::xfwd(P->n[2], P->iso, dim3(xblocks<T>(P), nb), P->stream, d, mode, P->rows, P->nvox, P->lam0,
-                         P->mu0));
+  HIPCHK(Launch<T>::xfwd(P->n[2], P->iso, dim3(xblocks<T>(P), nb), P->stream, d, mode, P->rows, P->nvox));
   return FFTH_OK;
 }
 
@@ -310,8 +318,7 @@ template <typename T> ffth_status yzy(ffth_plan* P, const Desc* d, int nb, int o
   const double scale = 1.0 / (double)P->nvox;
   {
     ProfScope ps(P, cz);
-    HIPCHK(Launch<T>::zpass(P->n[0], dim3((int)((M + tk - 1) / tk), nb), P->stream, d, op, P->n[1], P->h,
-                            P->lam0, P->mu0, scale));
+    HIPCHK(Launch<T>::zpass(P->n[0], dim3((int)((M + tk - 1) / tk), nb), P->stream, d, op, P->n[1], P->h, scale));
   }
   {
     ProfScope ps(P, cy);
@@ -322,14 +329,13 @@ template <typename T> ffth_status yzy(ffth_plan* P, const Desc* d, int nb, int o
 
 template <typename T> ffth_status xinv(ffth_plan* P, const Desc* d, int nb, int mode) {
   ProfScope ps(P, sizeof(T) == 8 ? C_XI64 : C_XI32);
-  HIPCHK(Launch<T>::xinv(P->n[2], P->iso, dim3(iblocks<T>(P), nb), P->stream, d, mode, P->rows, P->nvox, P->lam0,
-                         P->mu0));
+  HIPCHK(Launch<T>::xinv(P->n[2], P->iso, dim3(iblocks<T>(P), nb), P->stream, d, mode, P->rows, P->nvox));
   return FFTH_OK;
 }
 
 ffth_status fin(ffth_plan* P, const Desc* d, int nb, int op, int nblk_f, int nblk_i) {
   ProfScope ps(P, C_FIN);
-  HIPCHK(launch_finalize(nb, P->stream, d, op, nblk_f, nblk_i, P->lam0, P->mu0));
+  HIPCHK(launch_finalize(nb, P->stream, d, op, nblk_f, nblk_i));
   return FFTH_OK;
 }
 
@@ -337,6 +343,7 @@ ffth_status fin(ffth_plan* P, const Desc* d, int nb, int op, int nblk_f, int nbl
 template <typename T>
 ffth_status apply(ffth_plan* P, const Desc* d, int nb, int xf, int spec_op, int xi, int fin_op) {
   ffth_status s;
+  if (nb <= 0) return FFTH_OK;
   if ((s = xfwd<T>(P, d, nb, xf)) != FFTH_OK) return s;
   if (xf == XF_CG && (s = fin(P, d, nb, FIN_CG_ALPHA, xblocks<T>(P), 0)) != FFTH_OK) return s;
   if ((s = yzy<T>(P, d, nb, spec_op)) != FFTH_OK) return s;
@@ -351,6 +358,25 @@ bool any_active(ffth_plan* P, int first, int count) {
   return false;
 }
 
+// Launch set: the descriptors of role r for the loads whose state (slot
+// state_base + l) was active at the last read-back, copied contiguously into
+// compact region `region` so that grids span active loads only.  Loads that
+// finish before the next read-back are still launched and exit at once.
+struct DescSet {
+  const Desc* d;
+  int n;
+};
+DescSet active_set(ffth_plan* P, Role r, int state_base, int nl, int region) {
+  Desc* stage = P->h_cdesc + (size_t)region * P->nloads;
+  int k = 0;
+  for (int l = 0; l < nl; ++l)
+    if (P->h_state[state_base + l].active) stage[k++] = P->h_desc[desc_slot(P, r, l)];
+  Desc* dst = P->d_cdesc + (size_t)region * P->nloads;
+  if (k > 0 && !hip_ok(hipMemcpyAsync(dst, stage, k * sizeof(Desc), hipMemcpyHostToDevice, P->stream), "copy"))
+    return DescSet{nullptr, -1};
+  return DescSet{dst, k};
+}
+
 // ---- solve loops ----------------------------------------------------------
 
 // Iterate a plain (single precision level) scheme on descriptors d with
@@ -358,6 +384,7 @@ bool any_active(ffth_plan* P, int first, int count) {
 template <typename T> ffth_status run_plain(ffth_plan* P, const Desc* d, int nl) {
   const ffth_opts& o = P->opts;
   ffth_status s;
+  DescSet as;
   // pass 0: x = b = -Gamma0 * P_rhs, ||b||, zero right-hand-side guard
   if ((s = apply<T>(P, d, nl, XF_LS, OP_GAMMA, XI_BS, FIN_LS_FIRST)) != FFTH_OK) return s;
   if (o.scheme == FFTH_CG) {
@@ -368,9 +395,10 @@ template <typename T> ffth_status run_plain(ffth_plan* P, const Desc* d, int nl)
   int it = 0;
   while (it < o.max_iter && any_active(P, 0, nl)) {
     const int k = std::min(o.check_every, o.max_iter - it);
+    if ((as = active_set(P, R_MAIN, 0, nl, 0)).n < 0) return FFTH_ERR_DEVICE;
     for (int j = 0; j < k; ++j) {
-      if (o.scheme == FFTH_BASIC) s = apply<T>(P, d, nl, XF_LS, OP_GAMMA, XI_BS, FIN_BS);
-      else s = apply<T>(P, d, nl, XF_CG, OP_GAMMA, XI_CG, FIN_CG_BETA);
+      if (o.scheme == FFTH_BASIC) s = apply<T>(P, as.d, as.n, XF_LS, OP_GAMMA, XI_BS, FIN_BS);
+      else s = apply<T>(P, as.d, as.n, XF_CG, OP_GAMMA, XI_CG, FIN_CG_BETA);
       if (s != FFTH_OK) return s;
     }
     it += k;
@@ -379,57 +407,139 @@ template <typename T> ffth_status run_plain(ffth_plan* P, const Desc* d, int nl)
   return FFTH_OK;
 }
 
-// FP32 inner solves under an FP64 defect-correction loop.  Outer states in
-// [0, nl), inner states in [nl, 2nl).  eps (the FP64 iterate) zero on entry.
-ffth_status run_mixed(ffth_plan* P, int nl) {
-  const ffth_opts& o = P->opts;
-  ffth_status s;
-  int inner_total = 0;
-  for (int outer = 0; outer < o.max_outer; ++outer) {
-    // r = b - A x in FP64 (x += delta fused).  The first sweep has x = 0 and
-    // r = b, compatible: it goes straight to the FP32 inner right-hand side.
-    // Later sweeps keep r in FP64 and split it with the projection
-    // P = Gamma0 C0: the compatible part feeds the inner solve, the rest
-    // (minus the incompatible round-off of x) is applied to x directly.
-    if (outer == 0) s = apply<double>(P, dptr(P, R_MAIN), nl, XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER);
-    else s = apply<double>(P, dptr(P, R_MAIN_DELTA), nl, XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER_P);
-    if (s != FFTH_OK) return s;
-    if ((s = read_states(P)) != FFTH_OK) return s;
-    if (!any_active(P, 0, nl)) break;
-    if (outer == o.max_outer - 1) break;  // no sweep left to apply another correction
-    if (outer > 0) {
-      if ((s = apply<float>(P, dptr(P, R_PROJ), nl, XF_C0, OP_GAMMA, XI_PROJ, FIN_PROJ)) != FFTH_OK) return s;
-      if ((s = read_states(P)) != FFTH_OK) return s;   // FIN_PROJ activated the inner states
-    }
-    const Desc* di = dptr(P, R_INNER);
-    for (int l = 0; l < nl; ++l) {
-      const size_t bytes = (size_t)P->nvox * 6 * sizeof(float);
-      if (o.scheme == FFTH_CG) {
-        HIPCHK(hipMemsetAsync(f32_ptr(P, l, 0), 0, bytes, P->stream));          // delta = 0
-      } else {
-        HIPCHK(hipMemcpyAsync(f32_ptr(P, l, 0), f32_ptr(P, l, 1), bytes, hipMemcpyDeviceToDevice, P->stream));
-      }
-    }
-    int it = 0;
-    while (inner_total + it < o.max_iter && any_active(P, nl, nl)) {
-      const int k = std::min(o.check_every, o.max_iter - inner_total - it);
-      for (int j = 0; j < k; ++j) {
-        if (o.scheme == FFTH_BASIC) s = apply<float>(P, di, nl, XF_MATVEC, OP_GAMMA, XI_BS_INNER, FIN_BS);
-        else s = apply<float>(P, di, nl, XF_CG, OP_GAMMA, XI_CG, FIN_CG_BETA);
-        if (s != FFTH_OK) return s;
-      }
-      it += k;
-      if ((s = read_states(P)) != FFTH_OK) return s;
-    }
-    inner_total += it;
-    if (inner_total >= o.max_iter) {
-      // budget spent: one more FP64 sweep applies the last correction
-      const Desc* dmd = dptr(P, R_MAIN_DELTA);
-      if ((s = apply<double>(P, dmd, nl, XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER_P)) != FFTH_OK) return s;
-      if ((s = read_states(P)) != FFTH_OK) return s;
-      break;
+// ---- FP32 inner solves under an FP64 defect-correction loop -----------------
+//
+// A solve is a job stepping through phases.  One round advances every job of
+// a group (same grid and material kind) by one phase step, with the loads of
+// all jobs in the same phase sharing each launch:
+//   A0    first FP64 residual sweep (x = 0, r = b, compatible): straight to INNER
+//   A     FP64 residual sweep with x += delta fused, then PROJ
+//   PROJ  split r with P = Gamma0 C0: compatible part -> FP32 inner right-hand
+//         side, the rest (minus the incompatible round-off of x) applied to x
+//   INNER up to check_every FP32 CG / Basic Scheme iterations
+// Outer states sit in slots [0, nl), inner states in [nl, 2nl) of each plan.
+enum Phase { PH_A0 = 0, PH_A, PH_PROJ, PH_INNER, PH_DONE };
+
+struct Job {
+  ffth_plan* P = nullptr;
+  int nl = 0;
+  int phase = PH_A0;
+  int sweeps = 0;       // FP64 residual sweeps done
+  int inner_total = 0;  // FP32 inner iterations launched (budget: opts.max_iter)
+  bool last = false;    // inner budget spent: the next sweep is the final one
+};
+
+// Staging for combined descriptor arrays: 4 regions (one per phase kind) of
+// `cap` descriptors each, device copy + pinned host copy.
+struct Stage {
+  Desc* d;
+  Desc* h;
+  int cap;
+};
+
+// Append the descriptors of role r of job J whose state (slot base + l) was
+// active at the last read-back.
+int stage_append(Stage& st, int region, int count, const Job& J, Role r, int base) {
+  Desc* h = st.h + (size_t)region * st.cap;
+  for (int l = 0; l < J.nl && count < st.cap; ++l)
+    if (J.P->h_state[base + l].active) h[count++] = J.P->h_desc[desc_slot(J.P, r, l)];
+  return count;
+}
+
+ffth_status stage_upload(ffth_plan* dims, Stage& st, int region, int count, const Desc** out) {
+  *out = st.d + (size_t)region * st.cap;
+  if (count > 0)
+    HIPCHK(hipMemcpyAsync(st.d + (size_t)region * st.cap, st.h + (size_t)region * st.cap, count * sizeof(Desc),
+                          hipMemcpyHostToDevice, dims->stream));
+  return FFTH_OK;
+}
+
+ffth_status enter_inner(Job& J) {
+  ffth_plan* P = J.P;
+  const size_t bytes = (size_t)P->nvox * 6 * sizeof(float);
+  for (int l = 0; l < J.nl; ++l) {
+    if (P->opts.scheme == FFTH_CG) {
+      HIPCHK(hipMemsetAsync(f32_ptr(P, l, 0), 0, bytes, P->stream));  // delta = 0
+    } else {
+      HIPCHK(hipMemcpyAsync(f32_ptr(P, l, 0), f32_ptr(P, l, 1), bytes, hipMemcpyDeviceToDevice, P->stream));
     }
   }
+  J.phase = PH_INNER;
+  return FFTH_OK;
+}
+
+// One round for a group of mixed-precision jobs sharing grid size and material
+// kind (and stream).  Every job ends the round with its states read back.
+ffth_status group_round(std::vector<Job*>& jobs, Stage& st) {
+  if (jobs.empty()) return FFTH_OK;
+  ffth_plan* dims = jobs[0]->P;
+  const ffth_opts& o = dims->opts;
+  ffth_status s;
+  int nA0 = 0, nA = 0, nPR = 0, nIN = 0;
+  int kin = o.check_every;
+  for (Job* J : jobs) {
+    switch (J->phase) {
+      case PH_A0: nA0 = stage_append(st, 0, nA0, *J, R_MAIN, 0); break;
+      case PH_A: nA = stage_append(st, 1, nA, *J, R_MAIN_DELTA, 0); break;
+      case PH_PROJ: nPR = stage_append(st, 2, nPR, *J, R_PROJ, 0); break;
+      case PH_INNER:
+        nIN = stage_append(st, 3, nIN, *J, R_INNER, J->nl);
+        kin = std::min(kin, std::max(1, o.max_iter - J->inner_total));
+        break;
+    }
+  }
+  const Desc* d;
+  if ((s = stage_upload(dims, st, 0, nA0, &d)) != FFTH_OK) return s;
+  if ((s = apply<double>(dims, d, nA0, XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER)) != FFTH_OK) return s;
+  if ((s = stage_upload(dims, st, 1, nA, &d)) != FFTH_OK) return s;
+  if ((s = apply<double>(dims, d, nA, XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER_P)) != FFTH_OK) return s;
+  if ((s = stage_upload(dims, st, 2, nPR, &d)) != FFTH_OK) return s;
+  if ((s = apply<float>(dims, d, nPR, XF_C0, OP_GAMMA, XI_PROJ, FIN_PROJ)) != FFTH_OK) return s;
+  if ((s = stage_upload(dims, st, 3, nIN, &d)) != FFTH_OK) return s;
+  for (int j = 0; j < kin && nIN > 0; ++j) {
+    if (o.scheme == FFTH_BASIC) s = apply<float>(dims, d, nIN, XF_MATVEC, OP_GAMMA, XI_BS_INNER, FIN_BS);
+    else s = apply<float>(dims, d, nIN, XF_CG, OP_GAMMA, XI_CG, FIN_CG_BETA);
+    if (s != FFTH_OK) return s;
+  }
+  for (Job* J : jobs)
+    HIPCHK(hipMemcpyAsync(J->P->h_state, J->P->d_state, J->P->L.nstate * sizeof(SolverState),
+                          hipMemcpyDeviceToHost, dims->stream));
+  HIPCHK(hipStreamSynchronize(dims->stream));
+  for (Job* J : jobs) prof_flush(J->P);
+  // transitions
+  for (Job* J : jobs) {
+    ffth_plan* P = J->P;
+    switch (J->phase) {
+      case PH_A0:
+      case PH_A:
+        J->sweeps++;
+        if (!any_active(P, 0, J->nl) || J->last || J->sweeps >= o.max_outer) J->phase = PH_DONE;
+        else if (J->phase == PH_A0) {
+          if ((s = enter_inner(*J)) != FFTH_OK) return s;
+        } else J->phase = PH_PROJ;
+        break;
+      case PH_PROJ:
+        if ((s = enter_inner(*J)) != FFTH_OK) return s;
+        break;
+      case PH_INNER:
+        J->inner_total += kin;
+        if (J->inner_total >= o.max_iter) J->last = true;
+        if (!any_active(P, J->nl, J->nl) || J->last) J->phase = PH_A;
+        break;
+    }
+  }
+  return FFTH_OK;
+}
+
+ffth_status run_mixed(ffth_plan* P, int nl) {
+  Job J;
+  J.P = P;
+  J.nl = nl;
+  Stage st{P->d_cdesc, P->h_cdesc, P->nloads};
+  std::vector<Job*> jobs{&J};
+  ffth_status s;
+  while (J.phase != PH_DONE)
+    if ((s = group_round(jobs, st)) != FFTH_OK) return s;
   return FFTH_OK;
 }
 
@@ -510,7 +620,9 @@ void build_solve_descs(ffth_plan* P, int nl, const double* E, double* eps, bool 
 }
 
 // Run the solve for nl loads whose descriptors are built, then fill results.
-ffth_status solve_common(ffth_plan* P, int nl, double* eps, ffth_result* res, double t0, const double* gmean) {
+// Upload the iteration states and zero the iterate of nl loads whose
+// descriptors are built (keep_gscale: order-1 guard scales from the builder).
+ffth_status solve_begin(ffth_plan* P, int nl, bool keep_gscale) {
   const ffth_opts& o = P->opts;
   ffth_status s;
   const double guard = o.precision == FFTH_FP32 ? 1e-6 : 1e-14;
@@ -522,7 +634,7 @@ ffth_status solve_common(ffth_plan* P, int nl, double* eps, ffth_result* res, do
   }
   sts[3 * P->nloads] = make_state(0, 1, 0, 1);
   // keep the order-1 guard scales computed by the right-hand-side builder
-  if (gmean) {
+  if (keep_gscale) {
     if ((s = read_states(P)) != FFTH_OK) return s;
     for (int l = 0; l < nl; ++l) sts[l].gscale = P->h_state[2 * P->nloads + l].gscale;
   }
@@ -533,10 +645,13 @@ ffth_status solve_common(ffth_plan* P, int nl, double* eps, ffth_result* res, do
     const size_t bytes = (size_t)P->nvox * 6 * (o.precision == FFTH_FP32 ? sizeof(float) : sizeof(double));
     HIPCHK(hipMemsetAsync(m.x, 0, bytes, P->stream));
   }
-  if (o.precision == FFTH_FP64) s = run_plain<double>(P, dptr(P, R_MAIN), nl);
-  else if (o.precision == FFTH_FP32) s = run_plain<float>(P, dptr(P, R_MAIN), nl);
-  else s = run_mixed(P, nl);
-  if (s != FFTH_OK) return s;
+  return FFTH_OK;
+}
+
+// After the iteration: exact zero for guarded loads, volume averages, results.
+ffth_status solve_finish(ffth_plan* P, int nl, double* eps, ffth_result* res, double t0, const double* gmean) {
+  const ffth_opts& o = P->opts;
+  ffth_status s;
   // zero-rhs guard: eps = 0 exactly
   if ((s = read_states(P)) != FFTH_OK) return s;
   for (int l = 0; l < nl; ++l)
@@ -590,6 +705,16 @@ ffth_status solve_common(ffth_plan* P, int nl, double* eps, ffth_result* res, do
     if (r.status != FFTH_OK && worst == FFTH_OK) worst = (ffth_status)r.status;
   }
   return worst;
+}
+
+ffth_status solve_common(ffth_plan* P, int nl, double* eps, ffth_result* res, double t0, const double* gmean) {
+  ffth_status s;
+  if ((s = solve_begin(P, nl, gmean != nullptr)) != FFTH_OK) return s;
+  if (P->opts.precision == FFTH_FP64) s = run_plain<double>(P, dptr(P, R_MAIN), nl);
+  else if (P->opts.precision == FFTH_FP32) s = run_plain<float>(P, dptr(P, R_MAIN), nl);
+  else s = run_mixed(P, nl);
+  if (s != FFTH_OK) return s;
+  return solve_finish(P, nl, eps, res, t0, gmean);
 }
 
 double now_s() { return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count(); }
@@ -699,6 +824,7 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
   P->mat32 = (float*)(P->ws + L.mat32);
   P->d_desc = (Desc*)(P->ws + L.desc);
   P->d_state = (SolverState*)(P->ws + L.state);
+  P->d_cdesc = (Desc*)(P->ws + L.cdesc);
   P->nx64 = x_blocks(p->n[0], p->n[1], p->n[2], true, false);
   P->nx32 = x_blocks(p->n[0], p->n[1], p->n[2], false, false);
   P->ni64 = x_blocks(p->n[0], p->n[1], p->n[2], true, true);
@@ -706,6 +832,12 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
   P->h_desc.assign(L.ndesc, Desc{});
   if (!hip_ok(hipHostMalloc((void**)&P->h_state, L.nstate * sizeof(SolverState), hipHostMallocDefault),
               "hipHostMalloc")) {
+    delete P;
+    return FFTH_ERR_DEVICE;
+  }
+  if (!hip_ok(hipHostMalloc((void**)&P->h_cdesc, 4 * (size_t)nloads * sizeof(Desc), hipHostMallocDefault),
+              "hipHostMalloc")) {
+    (void)hipHostFree(P->h_state);
     delete P;
     return FFTH_ERR_DEVICE;
   }
@@ -742,12 +874,14 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
        hip_ok(hipStreamSynchronize(P->stream), "sync");
   if (!ok) {
     (void)hipHostFree(P->h_state);
+    (void)hipHostFree(P->h_cdesc);
     delete P;
     return FFTH_ERR_DEVICE;
   }
   if (hmax >= p->nphases) {
     g_last_error = "phase id " + std::to_string(hmax) + " >= nphases";
     (void)hipHostFree(P->h_state);
+    (void)hipHostFree(P->h_cdesc);
     delete P;
     return FFTH_ERR_INVALID;
   }
@@ -760,6 +894,7 @@ ffth_status ffth_plan_destroy(ffth_plan* P) {
   (void)hipStreamSynchronize(P->stream);
   prof_flush(P);
   for (hipEvent_t e : P->pool) (void)hipEventDestroy(e);
+  (void)hipHostFree(P->h_cdesc);
   (void)hipHostFree(P->h_state);
   delete P;
   return FFTH_OK;
@@ -983,6 +1118,291 @@ ffth_status ffth_profile_read(ffth_plan* P, int32_t category, int64_t* launches,
 
 const char* ffth_profile_name(int32_t category) {
   return (category >= 0 && category < NCAT) ? CAT_NAMES[category] : "";
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Serving: continuous batching of order-0 solves inside a caller-owned arena
+// ===========================================================================
+namespace {
+
+struct Request {
+  uint64_t id = 0;
+  int nl = 0;
+  int n[3] = {0, 0, 0};
+  bool iso = true;
+  ffth_problem prob{};
+  std::vector<double> table;      // host copy of lame / stiffness
+  std::vector<double> E;
+  size_t off = 0, bytes = 0, ws_bytes = 0;
+  ffth_plan* P = nullptr;
+  double* eps = nullptr;
+  Job job;
+  int state = 0;                  // 0 waiting, 1 running, 2 done, 3 cancelled
+  ffth_status status = FFTH_OK;
+  std::vector<ffth_result> res;
+  double t_submit = 0, t_start = 0;
+};
+
+size_t request_bytes(const int n[3], int nph, int nl, const ffth_opts& o, size_t* ws) {
+  int nn[3] = {n[0], n[1], n[2]};
+  const size_t w = make_layout(nn, nph, nl, 0, o).total;
+  if (ws) *ws = w;
+  const size_t nvox = (size_t)n[0] * n[1] * n[2];
+  return al(w) + al((size_t)nl * 6 * nvox * sizeof(double));
+}
+
+}  // namespace
+
+struct ffth_server {
+  char* arena = nullptr;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  ffth_opts opts{};
+  int max_running = 0;
+  Stage stage{nullptr, nullptr, 0};
+  std::map<size_t, size_t> free_;          // offset -> length of free arena ranges
+  std::deque<Request*> waiting;
+  std::vector<Request*> running;
+  std::map<uint64_t, Request*> reqs;
+  uint64_t next = 1;
+
+  bool alloc(size_t need, size_t* off) {
+    for (auto it = free_.begin(); it != free_.end(); ++it) {
+      if (it->second >= need) {
+        *off = it->first;
+        const size_t rest = it->second - need, at = it->first + need;
+        free_.erase(it);
+        if (rest) free_[at] = rest;
+        return true;
+      }
+    }
+    return false;
+  }
+  void release(size_t off, size_t len) {
+    auto it = free_.emplace(off, len).first;
+    auto nx = std::next(it);
+    if (nx != free_.end() && it->first + it->second == nx->first) {
+      it->second += nx->second;
+      free_.erase(nx);
+    }
+    if (it != free_.begin()) {
+      auto pv = std::prev(it);
+      if (pv->first + pv->second == it->first) {
+        pv->second += it->second;
+        free_.erase(it);
+      }
+    }
+  }
+};
+
+namespace {
+
+void finish_request(ffth_server* S, Request* r, ffth_status st) {
+  if (r->P) {
+    (void)ffth_plan_destroy(r->P);
+    r->P = nullptr;
+  }
+  if (r->bytes) S->release(r->off, r->bytes);
+  r->bytes = 0;
+  r->status = st;
+  r->state = st == FFTH_ERR_CANCELLED ? 3 : 2;
+}
+
+// Admit waiting requests in arrival order while their memory fits the arena
+// and a slot is free (head-of-line order is kept).
+ffth_status admit(ffth_server* S) {
+  while (!S->waiting.empty() && (int)S->running.size() < S->max_running) {
+    Request* r = S->waiting.front();
+    size_t off;
+    if (!S->alloc(r->bytes, &off)) break;
+    S->waiting.pop_front();
+    r->off = off;
+    r->prob.lame = r->iso ? r->table.data() : nullptr;
+    r->prob.stiffness = r->iso ? nullptr : r->table.data();
+    ffth_status st = ffth_plan_create(&r->P, &r->prob, &S->opts, r->nl, 0, S->arena + off, r->ws_bytes, S->stream);
+    if (st != FFTH_OK) {
+      r->P = nullptr;
+      finish_request(S, r, st);
+      continue;
+    }
+    r->eps = (double*)(S->arena + off + al(r->ws_bytes));
+    r->t_start = now_s();
+    build_solve_descs(r->P, r->nl, r->E.data(), r->eps, false);
+    if ((st = upload_descs(r->P)) != FFTH_OK || (st = solve_begin(r->P, r->nl, false)) != FFTH_OK) {
+      finish_request(S, r, st);
+      continue;
+    }
+    r->job = Job();
+    r->job.P = r->P;
+    r->job.nl = r->nl;
+    r->state = 1;
+    S->running.push_back(r);
+  }
+  return FFTH_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t ffth_request_bytes(const int32_t n[3], int32_t nphases, int32_t nloads, const ffth_opts* o) {
+  if (!n || !o || nloads < 1 || nphases < 1 || nphases > 65535) return 0;
+  for (int d = 0; d < 3; ++d)
+    if (!size_supported(n[d])) return 0;
+  if (!opts_valid(*o)) return 0;
+  int nn[3] = {n[0], n[1], n[2]};
+  return request_bytes(nn, nphases, nloads, *o, nullptr);
+}
+
+ffth_status ffth_server_create(ffth_server** out, void* arena, size_t arena_bytes, const ffth_opts* o,
+                               int32_t max_running, void* hip_stream) {
+  g_last_error.clear();
+  if (!out || !arena || !o || max_running < 1) {
+    g_last_error = "bad argument";
+    return FFTH_ERR_INVALID;
+  }
+  *out = nullptr;
+  if (((uintptr_t)arena) % ALIGN || !opts_valid(*o) || o->precision != FFTH_MIXED) {
+    g_last_error = "arena must be 256-byte aligned; serving runs the mixed-precision solver";
+    return FFTH_ERR_INVALID;
+  }
+  const int cap = 6 * max_running;
+  const size_t stage_bytes = al((size_t)4 * cap * sizeof(Desc));
+  if (arena_bytes <= stage_bytes) {
+    g_last_error = "arena too small";
+    return FFTH_ERR_OOM;
+  }
+  ffth_server* S = new ffth_server();
+  S->arena = (char*)arena;
+  S->bytes = arena_bytes;
+  S->stream = (hipStream_t)hip_stream;
+  S->opts = *o;
+  S->max_running = max_running;
+  S->stage.d = (Desc*)S->arena;
+  S->stage.cap = cap;
+  if (!hip_ok(hipHostMalloc((void**)&S->stage.h, (size_t)4 * cap * sizeof(Desc), hipHostMallocDefault),
+              "hipHostMalloc")) {
+    delete S;
+    return FFTH_ERR_DEVICE;
+  }
+  S->free_[stage_bytes] = arena_bytes - stage_bytes;
+  *out = S;
+  return FFTH_OK;
+}
+
+ffth_status ffth_submit(ffth_server* S, const ffth_problem* p, int32_t nloads, const double* E, uint64_t* id) {
+  g_last_error.clear();
+  if (!S || !p || !E || !id || nloads < 1 || nloads > 6) {
+    g_last_error = "bad argument (1..6 load cases per request)";
+    return FFTH_ERR_INVALID;
+  }
+  for (int d = 0; d < 3; ++d)
+    if (!size_supported(p->n[d])) {
+      g_last_error = "unsupported grid size";
+      return FFTH_ERR_INVALID;
+    }
+  if (p->nphases < 1 || p->nphases > 65535 || !p->phase || ((p->lame == nullptr) == (p->stiffness == nullptr))) {
+    g_last_error = "bad phase table";
+    return FFTH_ERR_INVALID;
+  }
+  Request* r = new Request();
+  r->id = S->next++;
+  r->nl = nloads;
+  for (int d = 0; d < 3; ++d) r->n[d] = p->n[d];
+  r->iso = p->lame != nullptr;
+  r->prob = *p;
+  const int per = r->iso ? 2 : 21;
+  r->table.assign(r->iso ? p->lame : p->stiffness, (r->iso ? p->lame : p->stiffness) + (size_t)per * p->nphases);
+  r->E.assign(E, E + 6 * nloads);
+  r->bytes = request_bytes(r->n, p->nphases, nloads, S->opts, &r->ws_bytes);
+  r->t_submit = now_s();
+  if (r->bytes > S->bytes - al((size_t)4 * S->stage.cap * sizeof(Desc))) {
+    delete r;
+    g_last_error = "request larger than the whole arena";
+    return FFTH_ERR_OOM;
+  }
+  S->reqs[r->id] = r;
+  S->waiting.push_back(r);
+  *id = r->id;
+  return FFTH_OK;
+}
+
+ffth_status ffth_server_step(ffth_server* S, int32_t* running, int32_t* waiting) {
+  g_last_error.clear();
+  if (!S) return FFTH_ERR_INVALID;
+  ffth_status st = admit(S);
+  if (st != FFTH_OK) return st;
+  // group running jobs by grid and material kind; one round per group
+  std::map<std::tuple<int, int, int, bool>, std::vector<Job*>> groups;
+  for (Request* r : S->running) groups[std::make_tuple(r->n[0], r->n[1], r->n[2], r->iso)].push_back(&r->job);
+  for (auto& kv : groups) {
+    std::vector<Job*>& all = kv.second;
+    const int per = std::max(1, S->stage.cap / 6);
+    for (size_t i = 0; i < all.size(); i += per) {
+      std::vector<Job*> chunk(all.begin() + i, all.begin() + std::min(all.size(), i + per));
+      if ((st = group_round(chunk, S->stage)) != FFTH_OK) return st;
+    }
+  }
+  // completed solves: volume averages, results, memory back to the arena
+  std::vector<Request*> still;
+  for (Request* r : S->running) {
+    if (r->job.phase != PH_DONE) {
+      still.push_back(r);
+      continue;
+    }
+    r->res.assign(r->nl, ffth_result{});
+    ffth_status fs = solve_finish(r->P, r->nl, r->eps, r->res.data(), r->t_submit, nullptr);
+    finish_request(S, r, fs);
+  }
+  S->running.swap(still);
+  if ((st = admit(S)) != FFTH_OK) return st;
+  if (running) *running = (int32_t)S->running.size();
+  if (waiting) *waiting = (int32_t)S->waiting.size();
+  return FFTH_OK;
+}
+
+ffth_status ffth_poll(ffth_server* S, uint64_t id, ffth_result* res) {
+  if (!S) return FFTH_ERR_INVALID;
+  auto it = S->reqs.find(id);
+  if (it == S->reqs.end()) return FFTH_ERR_INVALID;
+  Request* r = it->second;
+  if (r->state < 2) return FFTH_ERR_BUSY;
+  ffth_status st = r->status;
+  if (r->state == 2 && res)
+    for (int l = 0; l < r->nl; ++l) res[l] = r->res[l];
+  S->reqs.erase(it);
+  delete r;
+  return st;
+}
+
+ffth_status ffth_cancel(ffth_server* S, uint64_t id) {
+  if (!S) return FFTH_ERR_INVALID;
+  auto it = S->reqs.find(id);
+  if (it == S->reqs.end()) return FFTH_ERR_INVALID;
+  Request* r = it->second;
+  if (r->state >= 2) return FFTH_OK;
+  if (r->state == 0) {
+    S->waiting.erase(std::find(S->waiting.begin(), S->waiting.end(), r));
+  } else {
+    S->running.erase(std::find(S->running.begin(), S->running.end(), r));
+  }
+  finish_request(S, r, FFTH_ERR_CANCELLED);
+  return FFTH_OK;
+}
+
+ffth_status ffth_server_destroy(ffth_server* S) {
+  if (!S) return FFTH_ERR_INVALID;
+  for (auto& kv : S->reqs) {
+    Request* r = kv.second;
+    if (r->P) (void)ffth_plan_destroy(r->P);
+    delete r;
+  }
+  (void)hipStreamSynchronize(S->stream);
+  (void)hipHostFree(S->stage.h);
+  delete S;
+  return FFTH_OK;
 }
 
 }  // extern "C"

@@ -111,7 +111,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
 
 template <typename T, int N2, bool ISO, int ROWS = x_rows<T>(N2), int NTB = NT>
 __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, int mode, long rows_total,
-                                              long nvox, double lam0, double mu0) {
+                                              long nvox) {
   constexpr int RS = N2 + N2 / 16;
   constexpr int H = N2 / 2;
   __shared__ C2<T> z[ROWS * 3 * RS];
@@ -187,9 +187,9 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
         T v[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) v[c] = (T)vp[c * nvox + vox];
-        const T tr = (T)lam0 * (v[0] + v[1] + v[2]);
+        const T tr = (T)d.lam0 * (v[0] + v[1] + v[2]);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) tau[c] = T(2) * (T)mu0 * v[c] + (c < 3 ? tr : T(0));
+        for (int c = 0; c < 6; ++c) tau[c] = T(2) * (T)d.mu0 * v[c] + (c < 3 ? tr : T(0));
       } else {  // XF_COPY
         const double* ip = (const double*)d.io;
 #pragma unroll
@@ -225,8 +225,7 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
 // x-pass, inverse: complex-to-real FFT along axis 2 + update + reductions.
 // ---------------------------------------------------------------------------
 template <typename T, int N2, bool ISO, int ROWS = xi_rows<T>(N2), int NTB = NT>
-__global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, int mode, long rows_total, long nvox,
-                                              double lam0, double mu0) {
+__global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, int mode, long rows_total, long nvox) {
   constexpr int RS = N2 + N2 / 16;
   constexpr int H = N2 / 2;
   __shared__ C2<T> z[ROWS * 3 * RS];
@@ -302,7 +301,7 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
         for (int c = 0; c < 6; ++c) rp[c * nvox + vox] = (T)r[c];
       }
       acc0 += r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + 2.0 * (r[3] * r[3] + r[4] * r[4] + r[5] * r[5]);
-      acc1 += c0_ip(lam0, mu0, r, r);
+      acc1 += c0_ip(d.lam0, d.mu0, r, r);
     } else if (mode == XI_BS_INNER) {
       T* xp = (T*)d.x;
       const T* rp = (const T*)d.r;
@@ -330,7 +329,7 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
         op[c * nvox + vox] = (float)rc[c];
       }
       acc0 += rc[0] * rc[0] + rc[1] * rc[1] + rc[2] * rc[2] + 2.0 * (rc[3] * rc[3] + rc[4] * rc[4] + rc[5] * rc[5]);
-      acc1 += c0_ip(lam0, mu0, rc, rc);
+      acc1 += c0_ip(d.lam0, d.mu0, rc, rc);
     } else {  // XI_CG: q = p - eta; x += alpha p; r -= alpha q
       T* xp = (T*)d.x;
       T* rp = (T*)d.r;
@@ -345,7 +344,7 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
         rp[c * nvox + vox] = rv;
         r[c] = (double)rv;
       }
-      acc0 += c0_ip(lam0, mu0, r, r);
+      acc0 += c0_ip(d.lam0, d.mu0, r, r);
       acc1 += r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + 2.0 * (r[3] * r[3] + r[4] * r[4] + r[5] * r[5]);
     }
   }
@@ -472,8 +471,7 @@ __device__ __forceinline__ void spectral_op(int op, T (&in)[6][2], T (&out)[6][2
 }
 
 template <typename T, int N0, int TK = z_cols<T>(N0), int NTB = NT, bool REMAP = true, int V = vec_width<T>()>
-__global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, int op, int n1, int h, double lam0,
-                                               double mu0, double scale) {
+__global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, int op, int n1, int h, double scale) {
   constexpr int W = TK * 6;
   __shared__ __attribute__((aligned(16))) C2<T> buf[N0 * W];
   __shared__ C2<T> tw[N0];
@@ -520,7 +518,7 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
 #pragma unroll
       for (int c = 0; c < 6; ++c) out[c][0] = out[c][1] = T(0);
     } else {
-      spectral_op<T>(op, in, out, (T)k0s, (T)k1s, (T)k2, lam0, mu0, (T)scale);
+      spectral_op<T>(op, in, out, (T)k0s, (T)k1s, (T)k2, d.lam0, d.mu0, (T)scale);
     }
 #pragma unroll
     for (int c = 0; c < 6; c += V) {
@@ -547,8 +545,7 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
 // the scalar update of its iteration state.  One block per entry.
 // ---------------------------------------------------------------------------
 constexpr int NT_FIN = 1024;
-__global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ descs, int op, int nblk_f, int nblk_i,
-                                                     double lam0, double mu0);
+__global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ descs, int op, int nblk_f, int nblk_i);
 
 // Volume averages of sigma = P_rhs + C:x (or C:(E + x)): 6 sums per block.
 template <bool ISO>

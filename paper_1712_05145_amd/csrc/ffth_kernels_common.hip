@@ -34,8 +34,7 @@ __device__ static void fin_slots(int op, int& nf, int& ni) {
   }
 }
 
-__global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ descs, int op, int nblk_f, int nblk_i,
-                                                     double lam0, double mu0) {
+__global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ descs, int op, int nblk_f, int nblk_i) {
   const Desc& d = descs[blockIdx.x];
   SolverState* st = d.st;
   if (!st->active) return;
@@ -57,7 +56,7 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
   block_sums<NRED, NT_FIN>(ai, si);
   __syncthreads();
   if (threadIdx.x != 0) return;
-  const double amu = fabs(mu0);
+  const double amu = fabs(d.mu0);
   switch (op) {
     case FIN_LS_FIRST: {
       st->nb2 = si[0];
@@ -275,9 +274,8 @@ bool size_supported(int n) {
   return false;
 }
 
-hipError_t launch_finalize(int nbatch, hipStream_t s, const Desc* d, int op, int nblk_f, int nblk_i, double lam0,
-                           double mu0) {
-  hipLaunchKernelGGL(k_finalize, dim3(nbatch), dim3(NT_FIN), 0, s, d, op, nblk_f, nblk_i, lam0, mu0);
+hipError_t launch_finalize(int nbatch, hipStream_t s, const Desc* d, int op, int nblk_f, int nblk_i) {
+  hipLaunchKernelGGL(k_finalize, dim3(nbatch), dim3(NT_FIN), 0, s, d, op, nblk_f, nblk_i);
   return hipGetLastError();
 }
 

@@ -38,11 +38,11 @@ template <typename T> int Launch<T>::z_cols(int n) {
 }
 
 template <typename T> hipError_t Launch<T>::xfwd(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows,
-                                       long nvox, double lam0, double mu0) {
+                                       long nvox) {
 #define FFTH_CASE(N)                                                                                          \
   if (n2 == N) {                                                                                              \
-    if (iso) hipLaunchKernelGGL((k_xfwd<T, N, true>), grid, dim3(NT), 0, s, d, mode, rows, nvox, lam0, mu0);  \
-    else hipLaunchKernelGGL((k_xfwd<T, N, false>), grid, dim3(NT), 0, s, d, mode, rows, nvox, lam0, mu0);     \
+    if (iso) hipLaunchKernelGGL((k_xfwd<T, N, true>), grid, dim3(NT), 0, s, d, mode, rows, nvox);  \
+    else hipLaunchKernelGGL((k_xfwd<T, N, false>), grid, dim3(NT), 0, s, d, mode, rows, nvox);     \
     return hipGetLastError();                                                                                 \
   }
   FFTH_SIZES(FFTH_CASE)
@@ -51,11 +51,11 @@ template <typename T> hipError_t Launch<T>::xfwd(int n2, bool iso, dim3 grid, hi
 }
 
 template <typename T> hipError_t Launch<T>::xinv(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows,
-                                       long nvox, double lam0, double mu0) {
+                                       long nvox) {
 #define FFTH_CASE(N)                                                                                          \
   if (n2 == N) {                                                                                              \
-    if (iso) hipLaunchKernelGGL((k_xinv<T, N, true>), grid, dim3(NT), 0, s, d, mode, rows, nvox, lam0, mu0);  \
-    else hipLaunchKernelGGL((k_xinv<T, N, false>), grid, dim3(NT), 0, s, d, mode, rows, nvox, lam0, mu0);     \
+    if (iso) hipLaunchKernelGGL((k_xinv<T, N, true>), grid, dim3(NT), 0, s, d, mode, rows, nvox);  \
+    else hipLaunchKernelGGL((k_xinv<T, N, false>), grid, dim3(NT), 0, s, d, mode, rows, nvox);     \
     return hipGetLastError();                                                                                 \
   }
   FFTH_SIZES(FFTH_CASE)
@@ -76,10 +76,10 @@ template <typename T> hipError_t Launch<T>::ypass(int n1, dim3 grid, hipStream_t
 }
 
 template <typename T> hipError_t Launch<T>::zpass(int n0, dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h,
-                                        double lam0, double mu0, double scale) {
+                                        double scale) {
 #define FFTH_CASE(N)                                                                                   \
   if (n0 == N) {                                                                                       \
-    hipLaunchKernelGGL((k_zpass<T, N>), grid, dim3(NT), 0, s, d, op, n1, h, lam0, mu0, scale);         \
+    hipLaunchKernelGGL((k_zpass<T, N>), grid, dim3(NT), 0, s, d, op, n1, h, scale);         \
     return hipGetLastError();                                                                          \
   }
   FFTH_SIZES(FFTH_CASE)

@@ -16,19 +16,15 @@ template <typename T> struct Launch {
   static int xi_rows(int n);
   static int y_cols(int n);
   static int z_cols(int n);
-  static hipError_t xfwd(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox,
-                         double lam0, double mu0);
-  static hipError_t xinv(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox,
-                         double lam0, double mu0);
+  static hipError_t xfwd(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox);
+  static hipError_t xinv(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox);
   static hipError_t ypass(int n1, dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols, int ntiles);
-  static hipError_t zpass(int n0, dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h, double lam0,
-                          double mu0, double scale);
+  static hipError_t zpass(int n0, dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h, double scale);
 };
 
 
 // non-templated kernels (ffth_kernels_common.hip)
-hipError_t launch_finalize(int nbatch, hipStream_t s, const Desc* d, int op, int nblk_f, int nblk_i, double lam0,
-                           double mu0);
+hipError_t launch_finalize(int nbatch, hipStream_t s, const Desc* d, int op, int nblk_f, int nblk_i);
 hipError_t launch_mean_stress(bool iso, int nblk, int nbatch, hipStream_t s, const Desc* d, long nvox);
 hipError_t launch_order1_point(bool iso, int nblk, int nbatch, hipStream_t s, const Desc* d, const double* eps0,
                                const double* x1, long nvox);

@@ -47,6 +47,7 @@ struct Desc {
   double* part_i;          // [nblk][8] block sums of the inverse x-pass / pointwise kernels
   SolverState* st;         // gating state
   SolverState* st2;        // secondary state (outer -> inner set-up)
+  double lam0, mu0;        // reference medium of this entry's problem
   double E[6];             // macroscopic strain, tensor components
   double G[18];            // order-1 gradient load G[J*3 + j]
   int32_t nc;              // components of io (3 or 6)

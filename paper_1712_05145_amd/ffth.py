@@ -83,6 +83,19 @@ SIGNATURES = [
     ("ffth_profile_read", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     ("ffth_profile_name", ctypes.c_char_p, [ctypes.c_int32]),
+    ("ffth_request_bytes", ctypes.c_size_t,
+     [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ffth_opts)]),
+    ("ffth_server_create", ctypes.c_int,
+     [ctypes.POINTER(ctypes.c_void_p), ctypes.c_void_p, ctypes.c_size_t, ctypes.POINTER(ffth_opts), ctypes.c_int32,
+      ctypes.c_void_p]),
+    ("ffth_submit", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.POINTER(ffth_problem), ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+      ctypes.POINTER(ctypes.c_uint64)]),
+    ("ffth_server_step", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
+    ("ffth_poll", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ffth_result)]),
+    ("ffth_cancel", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
+    ("ffth_server_destroy", ctypes.c_int, [ctypes.c_void_p]),
     ("ffth_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("ffth_last_error", ctypes.c_char_p, []),
 ]
@@ -289,3 +302,44 @@ class Solver:
         gm = ffth_order1_rhs(self.plan, _dptr(eps0_six.contiguous()), np.asarray(G, np.float64).reshape(18),
                              _dptr(p))
         return p, gm
+
+
+def ffth_request_bytes(n, nphases, nloads, opts):
+    arr = (ctypes.c_int32 * 3)(*n)
+    return int(load().ffth_request_bytes(arr, nphases, nloads, ctypes.byref(opts)))
+
+
+def ffth_server_create(arena_ptr, nbytes, opts, max_running, stream_ptr=None):
+    srv = ctypes.c_void_p()
+    _check(load().ffth_server_create(ctypes.byref(srv), arena_ptr, nbytes, ctypes.byref(opts), max_running,
+                                     stream_ptr), "ffth_server_create")
+    return srv
+
+
+def ffth_submit(srv, problem, E):
+    e, ep = _darr(E)
+    rid = ctypes.c_uint64()
+    _check(load().ffth_submit(srv, ctypes.byref(problem), e.shape[0], ep, ctypes.byref(rid)), "ffth_submit")
+    return int(rid.value)
+
+
+def ffth_server_step(srv):
+    run, wait = ctypes.c_int32(), ctypes.c_int32()
+    _check(load().ffth_server_step(srv, ctypes.byref(run), ctypes.byref(wait)), "ffth_server_step")
+    return run.value, wait.value
+
+
+def ffth_poll(srv, rid, nloads):
+    """(status, results): status FFTH_ERR_BUSY while running."""
+    res = (ffth_result * nloads)()
+    st = load().ffth_poll(srv, rid, res)
+    return st, ([r.as_dict() for r in res] if st != FFTH_ERR_BUSY else None)
+
+
+def ffth_cancel(srv, rid):
+    _check(load().ffth_cancel(srv, rid), "ffth_cancel")
+
+
+def ffth_server_destroy(srv):
+    _check(load().ffth_server_destroy(srv), "ffth_server_destroy")
+

@@ -38,6 +38,26 @@ ALG_BYTES_F32 = {"xfwd_f32": 98.0, "ypass_f32": 48.0, "zpass_f32": 48.0, "xinv_f
 LAUNCHES_PER_ITER = {"xfwd_f32": 1, "ypass_f32": 2, "zpass_f32": 1, "xinv_f32": 1}
 
 
+def measured_traffic(cat):
+    """HBM bytes per load-launch of kernel category `cat` from the committed
+    counter summary, or None when the kernel sources changed since it was taken."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1712_05145_amd", "csrc", "*"))):
+        h.update(open(f, "rb").read())
+    path = os.path.join(ROOT, "profiles", "traffic_fp32_passes_voronoi256.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    if f"source-hash: {h.hexdigest()[:16]}" not in txt:
+        return None
+    for line in txt.splitlines():
+        if line.startswith(f"traffic-bytes-per-load-launch {cat}:"):
+            return float(line.split(":")[1])
+    return None
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -69,6 +89,44 @@ def cpu_baseline(n_sample, grains, seed):
                       f"{n_sample}^3 Voronoi polycrystal of the same generator, single thread, {dt:.1f} s"}
 
 
+def serving_run(count, rate, dev):
+    """Request stream: Poisson arrivals, grids 32^3..128^3, random-sphere
+    microstructures, six unit loads each, mixed CG to 1e-8, 64 GB arena."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    from paper_1712_05145_amd import microstructure as M
+    from paper_1712_05145_amd.serving import Server, replay
+
+    stream = M.serving_requests(count=count, rate=rate)
+
+    def gen(r):
+        ph, lame = M.overlapping_spheres(r["n"], r["fraction"], r["contrast"], r["seed"])
+        return r["id"], (ph, lame) + M.midpoint_reference(lame)
+
+    t = time.perf_counter()
+    with ThreadPoolExecutor(8) as ex:
+        inputs = dict(ex.map(gen, stream))
+    log(f"serving: {count} request microstructures in {time.perf_counter() - t:.1f}s")
+    srv = Server(64 << 30, max_running=64, device=dev)
+    wid = srv.submit(*inputs[0], np.eye(6))              # warm-up request
+    while srv.poll(wid)[0] == 6:
+        srv.step()
+    records, stats = replay(srv, stream, inputs)
+    srv.close()
+    offered = sum(r["voxel_iters"] for r in records) / stream[-1]["arrival"]
+    by_n = {}
+    for n in sorted({r["n"] for r in records}):
+        lat = [r["latency"] for r in records if r["n"] == n]
+        by_n[str(n)] = {"count": len(lat), "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
+                        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 1)}
+    log(f"serving: p50 {stats['latency_p50_ms']:.0f} ms, p99 {stats['latency_p99_ms']:.0f} ms")
+    return {"requests": count, "rate_per_s": rate, "loads_per_request": 6, "makespan_s": round(stats["makespan_s"], 2),
+            "latency_p50_ms": round(stats["latency_p50_ms"], 1), "latency_p99_ms": round(stats["latency_p99_ms"], 1),
+            "achieved_voxel_iters_per_s": round(stats["voxel_iters_per_s"], 1),
+            "offered_voxel_iters_per_s": round(offered, 1), "failed": stats["failed"], "by_grid": by_n,
+            "arena_bytes": 64 << 30, "max_running": 64}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -84,6 +142,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=128)
+    ap.add_argument("--no-serve", action="store_true", help="skip the request-stream (serving) measurement")
+    ap.add_argument("--serve-count", type=int, default=512)
+    ap.add_argument("--serve-rate", type=float, default=40.0)
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -182,8 +243,12 @@ def main():
             entry["alg_bytes_per_voxel"] = ALG_BYTES_F32[c]
             entry["achieved_GBs"] = round(ALG_BYTES_F32[c] * nvox * u / (ms * 1e-3) / 1e9, 1)
         kernels[c] = entry
+    t_unit = measured_traffic(cat)
+    upl = units / max(launches, 1)
     roofline = {"bound": "hbm", "kernel": cat, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if t_unit is None else round(t_unit * upl),
+                "traffic_per_load_launch": t_unit, "alg_bytes_per_load_launch": ALG_BYTES_F32[cat] * nvox,
                 "alg_bytes_per_voxel": ALG_BYTES_F32[cat], "units_per_launch": round(units / max(launches, 1), 3),
                 "avg_launch_ms": round(tot_ms / max(launches, 1), 4),
                 "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
@@ -227,6 +292,8 @@ def main():
         log(f"fp64 step {t64 * 1e3:.1f} ms, C_eff diff {diff.max():.2e}")
         del f0, f1, e0, e1
         torch.cuda.empty_cache()
+    if not args.no_serve:
+        line["serving"] = serving_run(args.serve_count, args.serve_rate, dev)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(args.cpu_n, args.grains, args.seed)
     print(json.dumps(line), flush=True)

@@ -304,25 +304,36 @@ template <typename T> ffth_status xfwd(ffth_plan* P, const Desc* d, int nb, int 
   return FFTH_OK;
 }
 
+// Half spectrum layout [h/kc][n0][n1][kc][6]: the y-pass sees n0*h/kc planes of
+// [n1][kc*6]; the z-pass sees h/kc chunks of [n0][n1*kc][6].
+int kchunk_host(int h) {
+  int c = h < 16 ? h : 16;
+  while (h % c) --c;
+  return c;
+}
+
 template <typename T> ffth_status yzy(ffth_plan* P, const Desc* d, int nb, int op) {
-  const int ncols = P->h * 6;
+  const int kc = kchunk_host(P->h);
+  const int ncols = kc * 6;
+  const int nplanes = P->n[0] * (P->h / kc);
   const int cw = Launch<T>::y_cols(P->n[1]);
   const int ntiles = (ncols + cw - 1) / cw;
   const int cy = sizeof(T) == 8 ? C_Y64 : C_Y32, cz = sizeof(T) == 8 ? C_Z64 : C_Z32;
   {
     ProfScope ps(P, cy);
-    HIPCHK(Launch<T>::ypass(P->n[1], dim3(P->n[0] * ntiles, nb), P->stream, d, -1, ncols, ntiles));
+    HIPCHK(Launch<T>::ypass(P->n[1], dim3(nplanes * ntiles, nb), P->stream, d, -1, ncols, ntiles));
   }
-  const long M = (long)P->n[1] * P->h;
+  const long M = (long)P->n[1] * kc;
   const int tk = Launch<T>::z_cols(P->n[0]);
   const double scale = 1.0 / (double)P->nvox;
   {
     ProfScope ps(P, cz);
-    HIPCHK(Launch<T>::zpass(P->n[0], dim3((int)((M + tk - 1) / tk), nb), P->stream, d, op, P->n[1], P->h, scale));
+    const int nzb = (int)((M + tk - 1) / tk) * (P->h / kc);
+    HIPCHK(Launch<T>::zpass(P->n[0], dim3(nzb, nb), P->stream, d, op, P->n[1], P->h, scale));
   }
   {
     ProfScope ps(P, cy);
-    HIPCHK(Launch<T>::ypass(P->n[1], dim3(P->n[0] * ntiles, nb), P->stream, d, +1, ncols, ntiles));
+    HIPCHK(Launch<T>::ypass(P->n[1], dim3(nplanes * ntiles, nb), P->stream, d, +1, ncols, ntiles));
   }
   return FFTH_OK;
 }

@@ -1,7 +1,9 @@
 // HIP kernels of one iteration of the Moulinec-Suquet Basic Scheme / its CG
 // form (Algorithm 1 and eq. (6) of arXiv:1712.05145), organised as five
-// HBM-streaming passes over a half spectrum stored as [n0][n1][n2/2][6]
-// complex:
+// HBM-streaming passes over a half spectrum (k2 < n2/2, six interleaved
+// components) stored k2-chunked as [k2 / KC][n0][n1][k2 % KC][6] complex,
+// KC = kchunk(n2/2) (at most 16): every z-column then strides KC*6*n1
+// complex values between rows instead of a whole plane:
 //
 //   x-pass (forward)   constitutive law / polarization tau (Algorithm 1, first
 //                      step; eq. (2)) fused with the real-to-complex FFT along
@@ -51,6 +53,17 @@ template <typename T> constexpr int z_cols(int n) {
   c = c > 16 ? 16 : c;
   return c < 1 ? 1 : pow2_floor(c);
 }
+// k2 values per chunk of the half-spectrum layout: largest divisor of h up to 16
+__host__ __device__ constexpr int kchunk(int h) {
+  int c = h < 16 ? h : 16;
+  while (h % c) --c;
+  return c;
+}
+// index of (row = i0*n1 + i1, k2, component c) in the chunked half spectrum
+__device__ __forceinline__ long spec_at(long row, int k2, int c, long rows, int kc) {
+  return ((long)(k2 / kc) * rows + row) * (kc * 6) + (k2 % kc) * 6 + c;
+}
+
 // vector width of LDS / global accesses in the y and z passes (1: measured
 // faster than 16-byte pairs, which halve the threads busy in each stage)
 template <typename T> constexpr int vec_width() { return 1; }
@@ -215,7 +228,7 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
     C2<T> o;
     if ((c & 1) == 0) o = (z1 + z2) * T(0.5);
     else o = C2<T>{(z1.y - z2.y) * T(0.5), -(z1.x - z2.x) * T(0.5)};
-    spec[row * (H * 6) + rem] = o;
+    spec[spec_at(row, k, c, rows_total, kchunk(H))] = o;
   }
   double sums[1] = {acc0};
   block_sums<1, NTB>(sums, d.part_f + blockIdx.x, gridDim.x);
@@ -242,7 +255,7 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
     const long row = row0 + rr;
     C2<T> a = {0, 0}, b = {0, 0};
     if (row < rows_total) {
-      const C2<T>* s = spec + row * (H * 6) + k * 6 + 2 * q;
+      const C2<T>* s = spec + spec_at(row, k, 2 * q, rows_total, kchunk(H));
       a = s[0];
       b = s[1];
     }
@@ -478,9 +491,14 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
   const Desc& d = descs[blockIdx.y];
   if (!d.st->active) return;
   build_twiddles<T, N0, NTB>(tw);
-  const long M = (long)n1 * h;
-  const long m0 = (long)(REMAP ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x) * TK;
-  C2<T>* spec = (C2<T>*)d.spec;
+  // columns (i1, k2 % kc) of one k2-chunk form a [N0][M][6] sub-array
+  const int kc = kchunk(h);
+  const long M = (long)n1 * kc;
+  const int bpc = (int)((M + TK - 1) / TK);            // blocks per chunk
+  const int bid = REMAP ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  const int chunk = bid / bpc;
+  const long m0 = (long)(bid % bpc) * TK;
+  C2<T>* spec = (C2<T>*)d.spec + (long)chunk * N0 * M * 6;
   for (int v = threadIdx.x; v < N0 * W / V; v += NTB) {
     const int i0 = v / (W / V), w = (v % (W / V)) * V;
     C2<T> a[V];
@@ -498,7 +516,7 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
     const int k0 = v / TK, col = v % TK;
     const long m = m0 + col;
     if (m >= M) continue;
-    const int k1 = (int)(m / h), k2 = (int)(m % h);
+    const int k1 = (int)(m / kc), k2 = chunk * kc + (int)(m % kc);
     const bool nyq = ((N0 % 2 == 0) && k0 == N0 / 2) || ((n1 % 2 == 0) && k1 == n1 / 2);
     const int k0s = k0 < (N0 + 1) / 2 ? k0 : k0 - N0;
     const int k1s = k1 < (n1 + 1) / 2 ? k1 : k1 - n1;

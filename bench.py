@@ -145,6 +145,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the request-stream (serving) measurement")
     ap.add_argument("--serve-count", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=40.0)
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -170,7 +171,7 @@ def main():
     def make(precision, order, nloads):
         return ffth.Solver(phase, lam0, mu0, lame=lame, nloads=nloads, order=order, scheme=args.scheme,
                            precision=precision, tol=args.tol, max_iter=50000, inner_tol=args.inner_tol, max_outer=30,
-                           check_every=8, device=dev)
+                           check_every=8, autotune=not args.no_autotune, device=dev)
 
     # achievable streaming bandwidth on this device (context for the roofline)
     buf_a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -186,8 +187,10 @@ def main():
     del buf_a, buf_b
     log(f"device copy bandwidth {copy_gbs:.0f} GB/s")
 
+    t = time.perf_counter()
     s0 = make("mixed", 0, 6)
     s1 = make("mixed", 1, 1)
+    log(f"plans (incl. tile autotuning) in {time.perf_counter() - t:.2f}s; tiles {s0.tile_variants}")
     eps0 = s0.field(6, 6)
     eps1 = s1.field(6, 1)
 
@@ -266,6 +269,8 @@ def main():
                        "p99": round(float(np.percentile(times, 99)) * 1e3, 2), "over": "timed steps"},
         "roofline": roofline,
         "kernels": kernels,
+        "tile_variants": dict(zip(["xfwd_f32", "xfwd_f64", "ypass_f32", "ypass_f64", "zpass_f32", "zpass_f64",
+                                   "xinv_f32", "xinv_f64"], s0.tile_variants)),
     }
     del s0, s1
     torch.cuda.empty_cache()

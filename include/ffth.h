@@ -98,6 +98,8 @@ typedef struct {
                                  the first also projects the residual onto compatible
                                  fields, one FP32 operator application)                */
   int32_t check_every;        /* iterations between host reads of the convergence flags */
+  int32_t autotune;           /* 1: time the compiled tile shapes of every pass at plan
+                                 creation (grids >= 64^3) and keep the fastest          */
 } ffth_opts;
 
 typedef struct {
@@ -115,7 +117,7 @@ typedef struct {
 typedef struct ffth_plan ffth_plan;
 
 /* Default options: CG, MIXED, tol 1e-8, max_iter 20000, inner_tol 1e-2,
- * max_outer 30, check_every 8. */
+ * max_outer 30, check_every 8, autotune 1. */
 void ffth_default_opts(ffth_opts *o);
 
 /* 1 if n (one axis length) is supported by the compiled FFT kernels. */
@@ -183,6 +185,12 @@ ffth_status ffth_order1_rhs(ffth_plan *plan, const double *eps0_six, const doubl
 ffth_status ffth_profile_enable(ffth_plan *plan, int32_t on);
 ffth_status ffth_profile_read(ffth_plan *plan, int32_t category, int64_t *launches, double *ms);
 const char *ffth_profile_name(int32_t category);
+/* Tile variant chosen per pass: out[2*pass + prec], pass 0..3 = x-forward, y,
+ * z, x-inverse; prec 0 = FP32, 1 = FP64 (variant 0 = the default shape). */
+ffth_status ffth_tile_variants(ffth_plan *plan, int32_t out[8]);
+/* Pin the tile variants (same layout; each in [0, 3)); results of every
+ * variant agree to rounding.  INVALID for a value out of range. */
+ffth_status ffth_set_tile_variants(ffth_plan *plan, const int32_t in[8]);
 
 /* ---- Serving: continuous batching of order-0 solves ----------------------
  * A server owns no device memory: the caller hands it one device arena (the

@@ -8,10 +8,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <deque>
 #include <tuple>
 #include <map>
+#include <mutex>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -54,10 +56,10 @@ struct Layout {
   int ndesc, nstate, nblk;
 };
 
-int x_blocks(int n0, int n1, int n2, bool dbl, bool inverse) {
+int x_blocks(int n0, int n1, int n2, bool dbl, bool inverse, int v) {
   const long rows = (long)n0 * n1;
-  const int r = inverse ? (dbl ? Launch<double>::xi_rows(n2) : Launch<float>::xi_rows(n2))
-                        : (dbl ? Launch<double>::x_rows(n2) : Launch<float>::x_rows(n2));
+  const int r = inverse ? (dbl ? Launch<double>::xi_rows(n2, v) : Launch<float>::xi_rows(n2, v))
+                        : (dbl ? Launch<double>::x_rows(n2, v) : Launch<float>::x_rows(n2, v));
   return r > 0 ? (int)((rows + r - 1) / r) : 0;
 }
 
@@ -69,9 +71,7 @@ Layout make_layout(const int n[3], int nph, int nloads, int order, const ffth_op
   const int prec = o.precision, scheme = o.scheme;
   L.ndesc = 7 * nloads + 8;
   L.nstate = 3 * nloads + 1;
-  L.nblk = std::max({x_blocks(n[0], n[1], n[2], true, false), x_blocks(n[0], n[1], n[2], false, false),
-                     x_blocks(n[0], n[1], n[2], true, true), x_blocks(n[0], n[1], n[2], false, true),
-                     ms_blocks(nvox)});
+  L.nblk = std::max((int)((long)n[0] * n[1]), ms_blocks(nvox));   // x-pass blocks of any variant (>= 1 row)
   // per-load FP32 / FP64 field counts
   if (prec == FFTH_FP32) L.nf32 = scheme == FFTH_CG ? 3 : 1;
   if (prec == FFTH_MIXED) L.nf32 = scheme == FFTH_CG ? 3 : 2;
@@ -155,6 +155,7 @@ struct ffth_plan {
   Desc* h_cdesc;          // pinned staging for them
   int nx64, nx32;         // forward x-pass blocks per precision
   int ni64, ni32;         // inverse x-pass blocks per precision
+  int var[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};   // tile variant per pass (xf, y, z, xi) and FP32/FP64
   std::vector<Desc> h_desc;
   // kernel timing (diagnostics): events bracket every launch when enabled
   bool prof = false;
@@ -166,6 +167,13 @@ struct ffth_plan {
 };
 
 namespace {
+
+void set_blocks(ffth_plan* P) {
+  P->nx32 = x_blocks(P->n[0], P->n[1], P->n[2], false, false, P->var[0][0]);
+  P->nx64 = x_blocks(P->n[0], P->n[1], P->n[2], true, false, P->var[0][1]);
+  P->ni32 = x_blocks(P->n[0], P->n[1], P->n[2], false, true, P->var[3][0]);
+  P->ni64 = x_blocks(P->n[0], P->n[1], P->n[2], true, true, P->var[3][1]);
+}
 
 double* part_ptr(ffth_plan* P, int slot) { return (double*)(P->ws + P->L.part + (size_t)slot * P->L.part_stride); }
 void* spec_ptr(ffth_plan* P, int l) { return P->ws + P->L.spec + (size_t)l * P->L.spec_stride; }
@@ -295,12 +303,16 @@ ffth_status read_states(ffth_plan* P) {
 
 // ---- pass launchers -------------------------------------------------------
 
+enum Pass { PS_XF = 0, PS_Y = 1, PS_Z = 2, PS_XI = 3 };
+template <typename T> int pv(ffth_plan* P, Pass ps) { return P->var[ps][sizeof(T) == 8 ? 1 : 0]; }
+
 template <typename T> int xblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->nx64 : P->nx32; }
 template <typename T> int iblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->ni64 : P->ni32; }
 
 template <typename T> ffth_status xfwd(ffth_plan* P, const Desc* d, int nb, int mode) {
   ProfScope ps(P, sizeof(T) == 8 ? C_XF64 : C_XF32);
-  HIPCHK(Launch<T>::xfwd(P->n[2], P->iso, dim3(xblocks<T>(P), nb), P->stream, d, mode, P->rows, P->nvox));
+  HIPCHK(Launch<T>::xfwd(P->n[2], P->iso, pv<T>(P, PS_XF), dim3(xblocks<T>(P), nb), P->stream, d, mode, P->rows,
+                         P->nvox));
   return FFTH_OK;
 }
 
@@ -316,37 +328,185 @@ template <typename T> ffth_status yzy(ffth_plan* P, const Desc* d, int nb, int o
   const int kc = kchunk_host(P->h);
   const int ncols = kc * 6;
   const int nplanes = P->n[0] * (P->h / kc);
-  const int cw = Launch<T>::y_cols(P->n[1]);
+  const int vy = pv<T>(P, PS_Y), vz = pv<T>(P, PS_Z);
+  const int cw = Launch<T>::y_cols(P->n[1], vy);
   const int ntiles = (ncols + cw - 1) / cw;
   const int cy = sizeof(T) == 8 ? C_Y64 : C_Y32, cz = sizeof(T) == 8 ? C_Z64 : C_Z32;
   {
     ProfScope ps(P, cy);
-    HIPCHK(Launch<T>::ypass(P->n[1], dim3(nplanes * ntiles, nb), P->stream, d, -1, ncols, ntiles));
+    HIPCHK(Launch<T>::ypass(P->n[1], vy, dim3(nplanes * ntiles, nb), P->stream, d, -1, ncols, ntiles));
   }
   const long M = (long)P->n[1] * kc;
-  const int tk = Launch<T>::z_cols(P->n[0]);
+  const int tk = Launch<T>::z_cols(P->n[0], vz);
   const double scale = 1.0 / (double)P->nvox;
   {
     ProfScope ps(P, cz);
     const int nzb = (int)((M + tk - 1) / tk) * (P->h / kc);
-    HIPCHK(Launch<T>::zpass(P->n[0], dim3(nzb, nb), P->stream, d, op, P->n[1], P->h, scale));
+    HIPCHK(Launch<T>::zpass(P->n[0], vz, dim3(nzb, nb), P->stream, d, op, P->n[1], P->h, scale));
   }
   {
     ProfScope ps(P, cy);
-    HIPCHK(Launch<T>::ypass(P->n[1], dim3(nplanes * ntiles, nb), P->stream, d, +1, ncols, ntiles));
+    HIPCHK(Launch<T>::ypass(P->n[1], vy, dim3(nplanes * ntiles, nb), P->stream, d, +1, ncols, ntiles));
   }
   return FFTH_OK;
 }
 
 template <typename T> ffth_status xinv(ffth_plan* P, const Desc* d, int nb, int mode) {
   ProfScope ps(P, sizeof(T) == 8 ? C_XI64 : C_XI32);
-  HIPCHK(Launch<T>::xinv(P->n[2], P->iso, dim3(iblocks<T>(P), nb), P->stream, d, mode, P->rows, P->nvox));
+  HIPCHK(Launch<T>::xinv(P->n[2], P->iso, pv<T>(P, PS_XI), dim3(iblocks<T>(P), nb), P->stream, d, mode, P->rows,
+                         P->nvox));
   return FFTH_OK;
 }
 
 ffth_status fin(ffth_plan* P, const Desc* d, int nb, int op, int nblk_f, int nblk_i) {
   ProfScope ps(P, C_FIN);
   HIPCHK(launch_finalize(nb, P->stream, d, op, nblk_f, nblk_i));
+  return FFTH_OK;
+}
+
+// ---- autotuner ------------------------------------------------------------
+//
+// Each pass has NVAR compiled tile shapes.  At plan creation every variant of
+// every pass the plan will run is timed on the plan's own workspace (HIP
+// events on its stream, in the modes the solver uses) and the fastest kept.
+// Choices are cached per (grid, material kind, precision, scheme) for the
+// process.  Grids below 64^3 keep the defaults (launch-bound).
+std::mutex g_tune_mu;
+std::map<std::array<int, 6>, std::array<int, 8>> g_tune_cache;
+
+template <class F> double time_launches(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F&& launch) {
+  launch();  // warm-up
+  (void)hipEventRecord(e0, st);
+  launch();
+  (void)hipEventRecord(e1, st);
+  (void)hipEventSynchronize(e1);
+  float ms = 0.f;
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  const int reps = std::max(3, std::min(50, (int)std::ceil(6.0 / std::max(ms, 1e-3f))));
+  (void)hipEventRecord(e0, st);
+  for (int i = 0; i < reps; ++i) launch();
+  (void)hipEventRecord(e1, st);
+  (void)hipEventSynchronize(e1);
+  (void)hipEventElapsedTime(&ms, e0, e1);
+  return ms / reps;
+}
+
+template <typename T> void tune_prec(ffth_plan* P, const Desc* d, int xf_mode, int xi_mode) {
+  const int pi = sizeof(T) == 8 ? 1 : 0;
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return;
+  }
+  const int kc = kchunk_host(P->h);
+  const int ncols = kc * 6, nplanes = P->n[0] * (P->h / kc);
+  const long M = (long)P->n[1] * kc;
+  for (int pass = 0; pass < 4; ++pass) {
+    double best = 1e30;
+    int bv = 0;
+    for (int v = 0; v < NVAR; ++v) {
+      P->var[pass][pi] = v;
+      set_blocks(P);
+      double t;
+      if (pass == PS_XF) {
+        t = time_launches(P->stream, e0, e1, [&] {
+          (void)Launch<T>::xfwd(P->n[2], P->iso, v, dim3(xblocks<T>(P), 1), P->stream, d, xf_mode, P->rows, P->nvox);
+        });
+      } else if (pass == PS_Y) {
+        const int cw = Launch<T>::y_cols(P->n[1], v), nt = (ncols + cw - 1) / cw;
+        t = time_launches(P->stream, e0, e1, [&] {
+          (void)Launch<T>::ypass(P->n[1], v, dim3(nplanes * nt, 1), P->stream, d, -1, ncols, nt);
+        });
+      } else if (pass == PS_Z) {
+        const int tk = Launch<T>::z_cols(P->n[0], v);
+        const int nzb = (int)((M + tk - 1) / tk) * (P->h / kc);
+        t = time_launches(P->stream, e0, e1, [&] {
+          (void)Launch<T>::zpass(P->n[0], v, dim3(nzb, 1), P->stream, d, OP_GAMMA, P->n[1], P->h,
+                                 1.0 / (double)P->nvox);
+        });
+      } else {
+        t = time_launches(P->stream, e0, e1, [&] {
+          (void)Launch<T>::xinv(P->n[2], P->iso, v, dim3(iblocks<T>(P), 1), P->stream, d, xi_mode, P->rows, P->nvox);
+        });
+      }
+      if (t < best * (v == 0 ? 1.0 : 0.98)) {   // a variant must beat the default by 2%
+        best = t;
+        bv = v;
+      }
+    }
+    P->var[pass][pi] = bv;
+  }
+  set_blocks(P);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
+ffth_status autotune(ffth_plan* P) {
+  const ffth_opts& o = P->opts;
+  if (!o.autotune || P->nvox < 64L * 64 * 64) return FFTH_OK;
+  const std::array<int, 6> key{P->n[0], P->n[1], P->n[2], P->iso ? 1 : 0, o.precision, o.scheme};
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune_cache.find(key);
+    if (it != g_tune_cache.end()) {
+      for (int i = 0; i < 8; ++i) P->var[i / 2][i % 2] = it->second[i];
+      set_blocks(P);
+      return FFTH_OK;
+    }
+  }
+  ffth_status s;
+  std::vector<SolverState> u(1, make_state(0, 1, 0, 1));
+  if ((s = upload_states(P, u, 3 * P->nloads)) != FFTH_OK) return s;
+  const Desc* dd = dptr(P, R_UTIL);
+  auto upload_one = [&](const Desc& d) -> ffth_status {
+    P->h_desc[desc_slot(P, R_UTIL, 0)] = d;
+    return upload_descs(P);
+  };
+  const bool mixed = o.precision == FFTH_MIXED;
+  if (o.precision != FFTH_FP64) {   // FP32 passes: the inner iteration (or the plain FP32 solve)
+    Desc d = base_desc(P, 0);
+    d.st = P->d_state + 3 * P->nloads;
+    int xf = XF_LS, xi = XI_BS;
+    d.x = f32_ptr(P, 0, 0);
+    if (P->L.nf32 >= 3) {
+      d.r = f32_ptr(P, 0, 1);
+      d.p = f32_ptr(P, 0, 2);
+      xf = XF_CG;
+      xi = XI_CG;
+    } else if (P->L.nf32 == 2) {
+      d.r = f32_ptr(P, 0, 1);
+      xf = XF_MATVEC;
+      xi = XI_BS_INNER;
+    }
+    if ((s = upload_one(d)) != FFTH_OK) return s;
+    tune_prec<float>(P, dd, xf, xi);
+  }
+  if (mixed || (o.precision == FFTH_FP64 && P->L.nf64 >= 2)) {   // FP64 passes
+    Desc d = base_desc(P, 0);
+    d.st = P->d_state + 3 * P->nloads;
+    int xf, xi;
+    d.x = f64_ptr(P, 0, 0);
+    if (mixed) {
+      d.r = f32_ptr(P, 0, 1);
+      d.r_f32 = 1;
+      xf = XF_LS;
+      xi = XI_RESID;
+    } else {
+      d.r = f64_ptr(P, 0, 0);
+      d.p = f64_ptr(P, 0, 1);
+      xf = XF_CG;
+      xi = XI_CG;
+    }
+    if ((s = upload_one(d)) != FFTH_OK) return s;
+    tune_prec<double>(P, dd, xf, xi);
+  }
+  HIPCHK(hipStreamSynchronize(P->stream));
+  HIPCHK(hipGetLastError());
+  std::array<int, 8> val;
+  for (int i = 0; i < 8; ++i) val[i] = P->var[i / 2][i % 2];
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_cache[key] = val;
   return FFTH_OK;
 }
 
@@ -746,6 +906,7 @@ void ffth_default_opts(ffth_opts* o) {
   o->inner_tol = 1e-2;
   o->max_outer = 30;
   o->check_every = 8;
+  o->autotune = 1;
 }
 
 int32_t ffth_size_supported(int32_t n) { return size_supported(n) ? 1 : 0; }
@@ -836,10 +997,7 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
   P->d_desc = (Desc*)(P->ws + L.desc);
   P->d_state = (SolverState*)(P->ws + L.state);
   P->d_cdesc = (Desc*)(P->ws + L.cdesc);
-  P->nx64 = x_blocks(p->n[0], p->n[1], p->n[2], true, false);
-  P->nx32 = x_blocks(p->n[0], p->n[1], p->n[2], false, false);
-  P->ni64 = x_blocks(p->n[0], p->n[1], p->n[2], true, true);
-  P->ni32 = x_blocks(p->n[0], p->n[1], p->n[2], false, true);
+  set_blocks(P);
   P->h_desc.assign(L.ndesc, Desc{});
   if (!hip_ok(hipHostMalloc((void**)&P->h_state, L.nstate * sizeof(SolverState), hipHostMallocDefault),
               "hipHostMalloc")) {
@@ -895,6 +1053,13 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
     (void)hipHostFree(P->h_cdesc);
     delete P;
     return FFTH_ERR_INVALID;
+  }
+  ffth_status ts = autotune(P);
+  if (ts != FFTH_OK) {
+    (void)hipHostFree(P->h_state);
+    (void)hipHostFree(P->h_cdesc);
+    delete P;
+    return ts;
   }
   *out = P;
   return FFTH_OK;
@@ -1124,6 +1289,26 @@ ffth_status ffth_profile_read(ffth_plan* P, int32_t category, int64_t* launches,
   prof_flush(P);
   *launches = P->prof_n[category];
   *ms = P->prof_ms[category];
+  return FFTH_OK;
+}
+
+ffth_status ffth_tile_variants(ffth_plan* P, int32_t out[8]) {
+  if (!P || !out) return FFTH_ERR_INVALID;
+  for (int i = 0; i < 8; ++i) out[i] = P->var[i / 2][i % 2];
+  return FFTH_OK;
+}
+
+ffth_status ffth_set_tile_variants(ffth_plan* P, const int32_t in[8]) {
+  g_last_error.clear();
+  if (!P || !in) return FFTH_ERR_INVALID;
+  for (int i = 0; i < 8; ++i) {
+    if (in[i] < 0 || in[i] >= NVAR) {
+      g_last_error = "tile variant out of range";
+      return FFTH_ERR_INVALID;
+    }
+  }
+  for (int i = 0; i < 8; ++i) P->var[i / 2][i % 2] = in[i];
+  set_blocks(P);
   return FFTH_OK;
 }
 

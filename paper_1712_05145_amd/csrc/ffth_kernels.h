@@ -53,6 +53,36 @@ template <typename T> constexpr int z_cols(int n) {
   c = c > 16 ? 16 : c;
   return c < 1 ? 1 : pow2_floor(c);
 }
+// Candidate shapes for the runtime autotuner: variant 0 is the measured
+// default above, 1 and 2 halve / double the tile (or swap the block size of
+// the y-pass), within 96 KB of LDS per block.
+template <typename T> constexpr int lds_cap_rows(int n) {          // x-pass rows within 96 KB
+  int r = 98304 / (3 * (n + n / 16) * (int)(2 * sizeof(T)));
+  return r < 1 ? 1 : pow2_floor(r);
+}
+template <typename T> constexpr int var_rows(int r0, int n, int v) {
+  int r = v == 1 ? (r0 > 1 ? r0 / 2 : 1) : v == 2 ? 2 * r0 : r0;
+  int c = lds_cap_rows<T>(n);
+  return r > c ? c : r;
+}
+template <typename T> constexpr int xf_rows_v(int n, int v) { return var_rows<T>(x_rows<T>(n), n, v); }
+template <typename T> constexpr int xi_rows_v(int n, int v) { return var_rows<T>(xi_rows<T>(n), n, v); }
+template <typename T> constexpr int y_cols_v(int n, int v) {
+  int c = y_cols<T>(n);
+  if (v == 2) c = c > 1 ? c / 2 : 1;
+  return c;
+}
+template <typename T> constexpr int y_threads_v(int n, int v) {
+  return v == 1 ? (y_threads<T>(n) == 512 ? 256 : 512) : v == 2 ? 256 : y_threads<T>(n);
+}
+template <typename T> constexpr int z_cols_v(int n, int v) {
+  int c = z_cols<T>(n);
+  c = v == 1 ? 2 * c : v == 2 ? (c > 1 ? c / 2 : 1) : c;
+  const int cap = 98304 / (n * 6 * (int)(2 * sizeof(T)));
+  c = c > cap ? (cap < 1 ? 1 : pow2_floor(cap)) : c;
+  return c;
+}
+
 // k2 values per chunk of the half-spectrum layout: largest divisor of h up to 16
 __host__ __device__ constexpr int kchunk(int h) {
   int c = h < 16 ? h : 16;

@@ -12,75 +12,105 @@ namespace ffth {
 
 using R = FFTH_REAL;
 
-template <typename T> int Launch<T>::x_rows(int n) {
-#define FFTH_CASE(N) if (n == N) return ffth::x_rows<T>(N);
+template <typename T> int Launch<T>::x_rows(int n, int v) {
+#define FFTH_CASE(N) if (n == N) return ffth::xf_rows_v<T>(N, v);
   FFTH_SIZES(FFTH_CASE)
 #undef FFTH_CASE
   return 0;
 }
-template <typename T> int Launch<T>::xi_rows(int n) {
-#define FFTH_CASE(N) if (n == N) return ffth::xi_rows<T>(N);
+template <typename T> int Launch<T>::xi_rows(int n, int v) {
+#define FFTH_CASE(N) if (n == N) return ffth::xi_rows_v<T>(N, v);
   FFTH_SIZES(FFTH_CASE)
 #undef FFTH_CASE
   return 0;
 }
-template <typename T> int Launch<T>::y_cols(int n) {
-#define FFTH_CASE(N) if (n == N) return ffth::y_cols<T>(N);
+template <typename T> int Launch<T>::y_cols(int n, int v) {
+#define FFTH_CASE(N) if (n == N) return ffth::y_cols_v<T>(N, v);
   FFTH_SIZES(FFTH_CASE)
 #undef FFTH_CASE
   return 0;
 }
-template <typename T> int Launch<T>::z_cols(int n) {
-#define FFTH_CASE(N) if (n == N) return ffth::z_cols<T>(N);
+template <typename T> int Launch<T>::z_cols(int n, int v) {
+#define FFTH_CASE(N) if (n == N) return ffth::z_cols_v<T>(N, v);
   FFTH_SIZES(FFTH_CASE)
 #undef FFTH_CASE
   return 0;
 }
 
-template <typename T> hipError_t Launch<T>::xfwd(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows,
-                                       long nvox) {
-#define FFTH_CASE(N)                                                                                          \
-  if (n2 == N) {                                                                                              \
-    if (iso) hipLaunchKernelGGL((k_xfwd<T, N, true>), grid, dim3(NT), 0, s, d, mode, rows, nvox);  \
-    else hipLaunchKernelGGL((k_xfwd<T, N, false>), grid, dim3(NT), 0, s, d, mode, rows, nvox);     \
-    return hipGetLastError();                                                                                 \
+// one launcher per (length, variant): the tile shape is a template argument
+template <typename T, int N, int V>
+static void xfwd_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox) {
+  constexpr int RW = ffth::xf_rows_v<T>(N, V);
+  if (iso) hipLaunchKernelGGL((k_xfwd<T, N, true, RW>), grid, dim3(NT), 0, s, d, mode, rows, nvox);
+  else hipLaunchKernelGGL((k_xfwd<T, N, false, RW>), grid, dim3(NT), 0, s, d, mode, rows, nvox);
+}
+template <typename T, int N, int V>
+static void xinv_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox) {
+  constexpr int RW = ffth::xi_rows_v<T>(N, V);
+  if (iso) hipLaunchKernelGGL((k_xinv<T, N, true, RW>), grid, dim3(NT), 0, s, d, mode, rows, nvox);
+  else hipLaunchKernelGGL((k_xinv<T, N, false, RW>), grid, dim3(NT), 0, s, d, mode, rows, nvox);
+}
+template <typename T, int N, int V>
+static void ypass_v(dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols, int ntiles) {
+  constexpr int CW = ffth::y_cols_v<T>(N, V);
+  constexpr int TB = ffth::y_threads_v<T>(N, V);
+  hipLaunchKernelGGL((k_ypass<T, N, CW, TB>), grid, dim3(TB), 0, s, d, dir, ncols, ntiles);
+}
+template <typename T, int N, int V>
+static void zpass_v(dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h, double scale) {
+  constexpr int TK = ffth::z_cols_v<T>(N, V);
+  hipLaunchKernelGGL((k_zpass<T, N, TK>), grid, dim3(NT), 0, s, d, op, n1, h, scale);
+}
+
+#define FFTH_VARIANTS(F, N, ...)          \
+  switch (v) {                            \
+    case 1: F<T, N, 1>(__VA_ARGS__); break; \
+    case 2: F<T, N, 2>(__VA_ARGS__); break; \
+    default: F<T, N, 0>(__VA_ARGS__);     \
+  }
+
+template <typename T> hipError_t Launch<T>::xfwd(int n2, bool iso, int v, dim3 grid, hipStream_t s, const Desc* d,
+                                                int mode, long rows, long nvox) {
+#define FFTH_CASE(N)                                                          \
+  if (n2 == N) {                                                              \
+    FFTH_VARIANTS(xfwd_v, N, iso, grid, s, d, mode, rows, nvox)              \
+    return hipGetLastError();                                                 \
   }
   FFTH_SIZES(FFTH_CASE)
 #undef FFTH_CASE
   return hipErrorInvalidValue;
 }
 
-template <typename T> hipError_t Launch<T>::xinv(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows,
-                                       long nvox) {
-#define FFTH_CASE(N)                                                                                          \
-  if (n2 == N) {                                                                                              \
-    if (iso) hipLaunchKernelGGL((k_xinv<T, N, true>), grid, dim3(NT), 0, s, d, mode, rows, nvox);  \
-    else hipLaunchKernelGGL((k_xinv<T, N, false>), grid, dim3(NT), 0, s, d, mode, rows, nvox);     \
-    return hipGetLastError();                                                                                 \
+template <typename T> hipError_t Launch<T>::xinv(int n2, bool iso, int v, dim3 grid, hipStream_t s, const Desc* d,
+                                                int mode, long rows, long nvox) {
+#define FFTH_CASE(N)                                                          \
+  if (n2 == N) {                                                              \
+    FFTH_VARIANTS(xinv_v, N, iso, grid, s, d, mode, rows, nvox)              \
+    return hipGetLastError();                                                 \
   }
   FFTH_SIZES(FFTH_CASE)
 #undef FFTH_CASE
   return hipErrorInvalidValue;
 }
 
-template <typename T> hipError_t Launch<T>::ypass(int n1, dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols,
-                                        int ntiles) {
-#define FFTH_CASE(N)                                                                                  \
-  if (n1 == N) {                                                                                      \
-    hipLaunchKernelGGL((k_ypass<T, N>), grid, dim3(ffth::y_threads<T>(N)), 0, s, d, dir, ncols, ntiles); \
-    return hipGetLastError();                                                                         \
+template <typename T> hipError_t Launch<T>::ypass(int n1, int v, dim3 grid, hipStream_t s, const Desc* d, int dir,
+                                                 int ncols, int ntiles) {
+#define FFTH_CASE(N)                                                          \
+  if (n1 == N) {                                                              \
+    FFTH_VARIANTS(ypass_v, N, grid, s, d, dir, ncols, ntiles)                \
+    return hipGetLastError();                                                 \
   }
   FFTH_SIZES(FFTH_CASE)
 #undef FFTH_CASE
   return hipErrorInvalidValue;
 }
 
-template <typename T> hipError_t Launch<T>::zpass(int n0, dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h,
-                                        double scale) {
-#define FFTH_CASE(N)                                                                                   \
-  if (n0 == N) {                                                                                       \
-    hipLaunchKernelGGL((k_zpass<T, N>), grid, dim3(NT), 0, s, d, op, n1, h, scale);         \
-    return hipGetLastError();                                                                          \
+template <typename T> hipError_t Launch<T>::zpass(int n0, int v, dim3 grid, hipStream_t s, const Desc* d, int op,
+                                                 int n1, int h, double scale) {
+#define FFTH_CASE(N)                                                          \
+  if (n0 == N) {                                                              \
+    FFTH_VARIANTS(zpass_v, N, grid, s, d, op, n1, h, scale)                  \
+    return hipGetLastError();                                                 \
   }
   FFTH_SIZES(FFTH_CASE)
 #undef FFTH_CASE

@@ -11,15 +11,20 @@ namespace ffth {
 
 bool size_supported(int n);
 
+// Every pass has NVAR compiled tile shapes (variant v); the plan picks one
+// per pass and precision (autotuned or the default 0).
 template <typename T> struct Launch {
-  static int x_rows(int n);
-  static int xi_rows(int n);
-  static int y_cols(int n);
-  static int z_cols(int n);
-  static hipError_t xfwd(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox);
-  static hipError_t xinv(int n2, bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox);
-  static hipError_t ypass(int n1, dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols, int ntiles);
-  static hipError_t zpass(int n0, dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h, double scale);
+  static int x_rows(int n, int v);
+  static int xi_rows(int n, int v);
+  static int y_cols(int n, int v);
+  static int z_cols(int n, int v);
+  static hipError_t xfwd(int n2, bool iso, int v, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows,
+                         long nvox);
+  static hipError_t xinv(int n2, bool iso, int v, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows,
+                         long nvox);
+  static hipError_t ypass(int n1, int v, dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols, int ntiles);
+  static hipError_t zpass(int n0, int v, dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h,
+                          double scale);
 };
 
 

@@ -68,5 +68,6 @@ enum : int32_t {
 };
 
 constexpr int NRED = 8;   // doubles per block in the partial-sum arrays
+constexpr int NVAR = 3;   // compiled tile shapes per pass (autotuner candidates)
 
 }  // namespace ffth

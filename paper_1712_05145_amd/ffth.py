@@ -41,7 +41,7 @@ class ffth_problem(ctypes.Structure):
 class ffth_opts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("precision", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
-                ("check_every", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("autotune", ctypes.c_int32)]
 
 
 class ffth_result(ctypes.Structure):
@@ -83,6 +83,8 @@ SIGNATURES = [
     ("ffth_profile_read", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
     ("ffth_profile_name", ctypes.c_char_p, [ctypes.c_int32]),
+    ("ffth_tile_variants", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    ("ffth_set_tile_variants", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     ("ffth_request_bytes", ctypes.c_size_t,
      [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ffth_opts)]),
     ("ffth_server_create", ctypes.c_int,
@@ -133,14 +135,26 @@ def _darr(a):
 
 
 def make_opts(scheme="cg", precision="mixed", tol=1e-8, max_iter=20000, inner_tol=1e-2, max_outer=30,
-              check_every=8):
+              check_every=8, autotune=True):
     o = ffth_opts()
     load().ffth_default_opts(ctypes.byref(o))
     o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else scheme
     o.precision = PRECISIONS[precision] if isinstance(precision, str) else precision
     o.tol, o.max_iter, o.inner_tol = tol, max_iter, inner_tol
     o.max_outer, o.check_every = max_outer, check_every
+    o.autotune = 1 if autotune else 0
     return o
+
+
+def ffth_tile_variants(plan):
+    out = (ctypes.c_int32 * 8)()
+    _check(load().ffth_tile_variants(plan, out), "ffth_tile_variants")
+    return list(out)
+
+
+def ffth_set_tile_variants(plan, variants):
+    arr = (ctypes.c_int32 * 8)(*[int(v) for v in variants])
+    _check(load().ffth_set_tile_variants(plan, arr), "ffth_set_tile_variants")
 
 
 def ffth_size_supported(n):
@@ -218,7 +232,7 @@ class Solver:
 
     def __init__(self, phase, lam0, mu0, lame=None, voigt21=None, nloads=1, order=0, scheme="cg",
                  precision="mixed", tol=1e-8, max_iter=20000, inner_tol=1e-2, max_outer=30, check_every=8,
-                 device="cuda:0", stream=None):
+                 autotune=True, device="cuda:0", stream=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -231,7 +245,7 @@ class Solver:
         self.nvox = int(np.prod(self.n))
         self.nloads = nloads
         self.order = order
-        self.opts = make_opts(scheme, precision, tol, max_iter, inner_tol, max_outer, check_every)
+        self.opts = make_opts(scheme, precision, tol, max_iter, inner_tol, max_outer, check_every, autotune)
         self._lame = None if lame is None else _darr(lame)
         self._v21 = None if voigt21 is None else _darr(voigt21)
         nph = (len(np.asarray(lame).reshape(-1, 2)) if lame is not None
@@ -262,6 +276,15 @@ class Solver:
             self.close()
         except Exception:
             pass
+
+    @property
+    def tile_variants(self):
+        """Tile variant per pass: [xf32, xf64, y32, y64, z32, z64, xi32, xi64]."""
+        return ffth_tile_variants(self.plan)
+
+    @tile_variants.setter
+    def tile_variants(self, v):
+        ffth_set_tile_variants(self.plan, v)
 
     def field(self, comps=6, nloads=1):
         return self.torch.empty((nloads, comps) + self.n, dtype=self.torch.float64, device=self.device)

@@ -288,3 +288,76 @@ def test_mixed_laminate_reaches_tight_tolerance_backus(scheme):
     ref = H.laminate_backus(lame[:, 0], lame[:, 1], f)
     assert all(r["status"] == 0 for r in res), [r["outer_iters"] for r in res]
     assert np.abs(ceff - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+
+VARIANT_SHAPES = [(12, 24, 8), (64, 48, 32), (32, 128, 24), (24, 32, 128), (256, 12, 16), (16, 256, 8),
+                  (16, 8, 256)]
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("shape", VARIANT_SHAPES)
+def test_every_tile_variant_green_parity(variant, shape):
+    """Each compiled tile shape of every pass gives the oracle's Gamma0 * tau."""
+    torch = require_gpu()
+    print("case green variant", variant, shape, flush=True)
+    rng = np.random.default_rng(7 + sum(shape))
+    tau = rng.standard_normal((6,) + shape)
+    ref = voigt6(spectral.green_apply(full(tau), 1.7, 0.9))
+    s = _uniform_solver(torch, shape, autotune=False)
+    s.tile_variants = [variant] * 8
+    assert s.tile_variants == [variant] * 8
+    for precision, tol in (("fp64", 1e-12), ("fp32", 5e-6)):
+        got = s.green_apply(to_dev(torch, tau), precision=precision).cpu().numpy()
+        assert rel_l2(got, ref) < tol, (precision, rel_l2(got, ref))
+
+
+def test_tile_variant_out_of_range_rejected():
+    torch = require_gpu()
+    s = _uniform_solver(torch, (8, 8, 8))
+    with pytest.raises(ffth.FFTHError):
+        s.tile_variants = [0, 0, 3, 0, 0, 0, 0, 0]
+    assert s.tile_variants == [0] * 8
+
+
+@pytest.mark.parametrize("variant", [1, 2])
+@pytest.mark.parametrize("scheme", ["cg", "basic"])
+def test_every_tile_variant_solve_parity(sphere16_oracle, variant, scheme):
+    """Mixed solves with every pass on a non-default tile shape (all fused
+    update and reduction modes) still match the oracle."""
+    torch = require_gpu()
+    print("case solve variant", variant, scheme, flush=True)
+    phase, lame, lam0, mu0, ceff, corr, _ = sphere16_oracle
+    s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, scheme=scheme, precision="mixed", tol=1e-10,
+                    max_iter=5000)
+    s.tile_variants = [variant] * 8
+    eps, res = s.solve_order0(np.eye(6))
+    eps = eps.cpu().numpy()
+    assert all(r["status"] == 0 for r in res)
+    for J in range(6):
+        assert rel_l2(eps[J], voigt6(corr[J])) < 1e-6, J
+    _, ok = _ceff_close(np.array([r["mean_stress"] for r in res]).T, ceff)
+    assert ok
+
+
+def test_autotuned_plan_matches_default_tiles():
+    """The tuner's choice at 64^3 is a valid variant set and the solve agrees
+    with the default tiles (same operator, reductions in another order)."""
+    torch = require_gpu()
+    print("case autotune 64", flush=True)
+    phase, lame = M.random_spheres(64, 8, seed=5)
+    lam0, mu0 = M.midpoint_reference(lame)
+    out = {}
+    for tune in (True, False):
+        s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, precision="mixed", tol=1e-9, autotune=tune)
+        v = s.tile_variants
+        print("variants", tune, v, flush=True)
+        assert len(v) == 8 and all(0 <= x < 3 for x in v)
+        if not tune:
+            assert v == [0] * 8
+        _, res = s.solve_order0(np.eye(6))
+        assert all(r["status"] == 0 for r in res)
+        out[tune] = np.array([r["mean_stress"] for r in res]).T
+        s.close()
+    d = np.sqrt(np.outer(np.diag(out[False]), np.diag(out[False])))
+    assert np.all(np.abs(out[True] - out[False]) <= 1e-8 * d)

@@ -28,14 +28,15 @@ sys.path.insert(0, ROOT)
 METRIC = "voxel-iters/s at 256^3, mixed vs FP64 to 1e-8 residual; p50/p99 solve latency"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic HBM bytes per voxel for one load in one launch of each kernel
-# category (FP32 CG inner iteration; 4-byte words, 2-byte phase ids):
-#   x-pass forward  r, p, phase read; p, half spectrum written   24+24+2+24+24
-#   y-pass / z-pass half spectrum (6 x n/2 complex) read and written  24+24
-#   x-pass inverse  spectrum, p, x, r read; x, r written          24*4+24*2
-ALG_BYTES_F32 = {"xfwd_f32": 98.0, "ypass_f32": 48.0, "zpass_f32": 48.0, "xinv_f32": 144.0}
-# launches of each category per load per inner iteration
-LAUNCHES_PER_ITER = {"xfwd_f32": 1, "ypass_f32": 2, "zpass_f32": 1, "xinv_f32": 1}
+# Algorithmic HBM bytes per voxel for one load in one launch of the FP32
+# kernel categories whose traffic does not depend on the mode (4-byte words,
+# 2-byte phase ids; the half spectrum is 6 x n/2 complex = 24 B per voxel):
+#   y-pass / z-pass        spectrum read and written                 24+24
+#   fused three-term CG    spectrum, r_k, x_k, r_k-1, x_k-1, phase read;
+#   x-pass                 r_k+1, x_k+1, spectrum written            24*5+2+24*3
+# (the FP32 x-forward / x-inverse categories mix the projection and start
+# passes, whose traffic differs by mode, and are reported without a model)
+ALG_BYTES_F32 = {"ypass_f32": 48.0, "zpass_f32": 48.0, "xcg3_f32": 194.0}
 
 
 def measured_traffic(cat):
@@ -229,20 +230,19 @@ def main():
     ms_step = elapsed / args.steps * 1e3
     ceff = np.array([r["mean_stress"] for r in results[-1][:6]]).T
 
-    # roofline of the dominant kernel (FP32 inner-iteration kernels)
-    prof = {k: (prof0[k][0] + prof1[k][0], prof0[k][1] + prof1[k][1]) for k in prof0}
-    inner_units = inner  # load-iterations processed by each FP32 category, per launch kind
+    # roofline of the dominant kernel; units = loads processed by its launches
+    prof = {k: (prof0[k][0] + prof1[k][0], prof0[k][1] + prof1[k][1], prof0[k][2] + prof1[k][2]) for k in prof0}
     cat = max(ALG_BYTES_F32, key=lambda c: prof[c][1])
-    launches, tot_ms = prof[cat]
-    units = inner_units * LAUNCHES_PER_ITER[cat]
+    launches, tot_ms, units = prof[cat]
     bytes_total = ALG_BYTES_F32[cat] * nvox * units
     achieved = bytes_total / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
     kernels = {}
     for c in prof:
-        n_l, ms = prof[c]
-        entry = {"launches": n_l, "total_ms": round(ms, 3), "avg_ms": round(ms / n_l, 4) if n_l else None}
+        n_l, ms, u = prof[c]
+        entry = {"launches": n_l, "loads": u, "total_ms": round(ms, 3),
+                 "avg_ms": round(ms / n_l, 4) if n_l else None,
+                 "ms_per_load": round(ms / u, 4) if u else None}
         if c in ALG_BYTES_F32 and ms > 0:
-            u = inner_units * LAUNCHES_PER_ITER[c]
             entry["alg_bytes_per_voxel"] = ALG_BYTES_F32[c]
             entry["achieved_GBs"] = round(ALG_BYTES_F32[c] * nvox * u / (ms * 1e-3) / 1e9, 1)
         kernels[c] = entry
@@ -252,7 +252,7 @@ def main():
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if t_unit is None else round(t_unit * upl),
                 "traffic_per_load_launch": t_unit, "alg_bytes_per_load_launch": ALG_BYTES_F32[cat] * nvox,
-                "alg_bytes_per_voxel": ALG_BYTES_F32[cat], "units_per_launch": round(units / max(launches, 1), 3),
+                "alg_bytes_per_voxel": ALG_BYTES_F32[cat], "units_per_launch": round(upl, 3),
                 "avg_launch_ms": round(tot_ms / max(launches, 1), 4),
                 "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 

@@ -179,11 +179,14 @@ ffth_status ffth_order1_rhs(ffth_plan *plan, const double *eps0_six, const doubl
 
 /* Kernel timing (diagnostics).  When enabled, every kernel launch of the plan
  * is bracketed by HIP events recorded on the plan's stream; the totals per
- * kernel category (0 .. 9: x-pass forward / y-pass / z-pass / x-pass inverse
- * in FP32, the same four in FP64, finalize, pointwise) accumulate until the
- * next ffth_profile_enable call, which also resets them. */
+ * kernel category (0 .. 10: x-pass forward / y-pass / z-pass / x-pass inverse
+ * in FP32, the same four in FP64, finalize, pointwise, fused three-term CG
+ * x-pass) accumulate until the next ffth_profile_enable call, which also
+ * resets them.  launches: kernel launches; units: batch entries (loads) they
+ * processed, summed; ms: summed event time. */
 ffth_status ffth_profile_enable(ffth_plan *plan, int32_t on);
-ffth_status ffth_profile_read(ffth_plan *plan, int32_t category, int64_t *launches, double *ms);
+ffth_status ffth_profile_read(ffth_plan *plan, int32_t category, int64_t *launches, int64_t *units,
+                              double *ms);
 const char *ffth_profile_name(int32_t category);
 /* Tile variant chosen per pass: out[2*pass + prec], pass 0..3 = x-forward, y,
  * z, x-inverse; prec 0 = FP32, 1 = FP64 (variant 0 = the default shape). */

@@ -20,6 +20,7 @@
 #include <string>
 #include <vector>
 
+#include "arena.h"
 #include "ffth.h"
 #include "ffth_launch.h"
 #include "ffth_types.h"
@@ -74,7 +75,7 @@ Layout make_layout(const int n[3], int nph, int nloads, int order, const ffth_op
   L.nblk = std::max((int)((long)n[0] * n[1]), ms_blocks(nvox));   // x-pass blocks of any variant (>= 1 row)
   // per-load FP32 / FP64 field counts
   if (prec == FFTH_FP32) L.nf32 = scheme == FFTH_CG ? 3 : 1;
-  if (prec == FFTH_MIXED) L.nf32 = scheme == FFTH_CG ? 3 : 2;
+  if (prec == FFTH_MIXED) L.nf32 = scheme == FFTH_CG ? 4 : 2;   // three-term CG: x, r in two slots each
   if (prec == FFTH_FP64) L.nf64 = scheme == FFTH_CG ? 2 : 0;
   if (prec == FFTH_MIXED) L.nf64 = 1;   // FP64 residual before its compatible projection
   L.spec_stride = al((size_t)nvox * 6 * sizeof(double));     // 6 x (nvox/2) complex FP64
@@ -159,11 +160,12 @@ struct ffth_plan {
   std::vector<Desc> h_desc;
   // kernel timing (diagnostics): events bracket every launch when enabled
   bool prof = false;
-  struct Rec { int cat; hipEvent_t a, b; };
+  struct Rec { int cat, units; hipEvent_t a, b; };
   std::vector<Rec> recs;
   std::vector<hipEvent_t> pool;
   double prof_ms[16] = {0};
   long prof_n[16] = {0};
+  long prof_units[16] = {0};   // batch entries (loads) processed, summed over launches
 };
 
 namespace {
@@ -202,9 +204,10 @@ const Desc* dptr(ffth_plan* P, Role r) { return P->d_desc + desc_slot(P, r, 0); 
 int util6_slot(ffth_plan* P, int J) { return 7 * P->nloads + J; }
 
 // ---- kernel timing ---------------------------------------------------------
-enum Cat { C_XF32 = 0, C_Y32, C_Z32, C_XI32, C_XF64, C_Y64, C_Z64, C_XI64, C_FIN, C_POINT, NCAT };
+enum Cat { C_XF32 = 0, C_Y32, C_Z32, C_XI32, C_XF64, C_Y64, C_Z64, C_XI64, C_FIN, C_POINT, C_XCG3, NCAT };
 const char* const CAT_NAMES[NCAT] = {"xfwd_f32", "ypass_f32", "zpass_f32", "xinv_f32", "xfwd_f64",
-                                     "ypass_f64", "zpass_f64", "xinv_f64", "finalize", "pointwise"};
+                                     "ypass_f64", "zpass_f64", "xinv_f64", "finalize", "pointwise",
+                                     "xcg3_f32"};
 
 hipEvent_t take_event(ffth_plan* P) {
   if (P->pool.empty()) {
@@ -218,9 +221,9 @@ hipEvent_t take_event(ffth_plan* P) {
 }
 
 // Bracket one launch: call before (returns the record index or -1) and after.
-int prof_begin(ffth_plan* P, int cat) {
+int prof_begin(ffth_plan* P, int cat, int units) {
   if (!P->prof) return -1;
-  ffth_plan::Rec r{cat, take_event(P), take_event(P)};
+  ffth_plan::Rec r{cat, units, take_event(P), take_event(P)};
   if (!r.a || !r.b) return -1;
   (void)hipEventRecord(r.a, P->stream);
   P->recs.push_back(r);
@@ -236,6 +239,7 @@ void prof_flush(ffth_plan* P) {
     if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
       P->prof_ms[r.cat] += ms;
       P->prof_n[r.cat] += 1;
+      P->prof_units[r.cat] += r.units;
     }
     P->pool.push_back(r.a);
     P->pool.push_back(r.b);
@@ -246,7 +250,7 @@ void prof_flush(ffth_plan* P) {
 struct ProfScope {
   ffth_plan* P;
   int idx;
-  ProfScope(ffth_plan* p, int cat) : P(p), idx(prof_begin(p, cat)) {}
+  ProfScope(ffth_plan* p, int cat, int units) : P(p), idx(prof_begin(p, cat, units)) {}
   ~ProfScope() { prof_end(P, idx); }
 };
 
@@ -310,7 +314,7 @@ template <typename T> int xblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->nx6
 template <typename T> int iblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->ni64 : P->ni32; }
 
 template <typename T> ffth_status xfwd(ffth_plan* P, const Desc* d, int nb, int mode) {
-  ProfScope ps(P, sizeof(T) == 8 ? C_XF64 : C_XF32);
+  ProfScope ps(P, sizeof(T) == 8 ? C_XF64 : C_XF32, nb);
   HIPCHK(Launch<T>::xfwd(P->n[2], P->iso, pv<T>(P, PS_XF), dim3(xblocks<T>(P), nb), P->stream, d, mode, P->rows,
                          P->nvox));
   return FFTH_OK;
@@ -333,35 +337,56 @@ template <typename T> ffth_status yzy(ffth_plan* P, const Desc* d, int nb, int o
   const int ntiles = (ncols + cw - 1) / cw;
   const int cy = sizeof(T) == 8 ? C_Y64 : C_Y32, cz = sizeof(T) == 8 ? C_Z64 : C_Z32;
   {
-    ProfScope ps(P, cy);
+    ProfScope ps(P, cy, nb);
     HIPCHK(Launch<T>::ypass(P->n[1], vy, dim3(nplanes * ntiles, nb), P->stream, d, -1, ncols, ntiles));
   }
   const long M = (long)P->n[1] * kc;
   const int tk = Launch<T>::z_cols(P->n[0], vz);
   const double scale = 1.0 / (double)P->nvox;
   {
-    ProfScope ps(P, cz);
+    ProfScope ps(P, cz, nb);
     const int nzb = (int)((M + tk - 1) / tk) * (P->h / kc);
     HIPCHK(Launch<T>::zpass(P->n[0], vz, dim3(nzb, nb), P->stream, d, op, P->n[1], P->h, scale));
   }
   {
-    ProfScope ps(P, cy);
+    ProfScope ps(P, cy, nb);
     HIPCHK(Launch<T>::ypass(P->n[1], vy, dim3(nplanes * ntiles, nb), P->stream, d, +1, ncols, ntiles));
   }
   return FFTH_OK;
 }
 
 template <typename T> ffth_status xinv(ffth_plan* P, const Desc* d, int nb, int mode) {
-  ProfScope ps(P, sizeof(T) == 8 ? C_XI64 : C_XI32);
+  ProfScope ps(P, sizeof(T) == 8 ? C_XI64 : C_XI32, nb);
   HIPCHK(Launch<T>::xinv(P->n[2], P->iso, pv<T>(P, PS_XI), dim3(iblocks<T>(P), nb), P->stream, d, mode, P->rows,
                          P->nvox));
   return FFTH_OK;
 }
 
 ffth_status fin(ffth_plan* P, const Desc* d, int nb, int op, int nblk_f, int nblk_i) {
-  ProfScope ps(P, C_FIN);
+  ProfScope ps(P, C_FIN, nb);
   HIPCHK(launch_finalize(nb, P->stream, d, op, nblk_f, nblk_i));
   return FFTH_OK;
+}
+
+// Start of a three-term CG inner solve: tau(r_0), its x-transform and the scalars.
+ffth_status cg3_start(ffth_plan* P, const Desc* d, int nb) {
+  ffth_status s;
+  if (nb <= 0) return FFTH_OK;
+  if ((s = xfwd<float>(P, d, nb, XF_R3)) != FFTH_OK) return s;
+  return fin(P, d, nb, FIN_CG3_INIT, xblocks<float>(P), 0);
+}
+
+// One three-term CG iteration: y, z (Green operator), y, fused x-pass, scalars.
+ffth_status cg3_iter(ffth_plan* P, const Desc* d, int nb) {
+  ffth_status s;
+  if (nb <= 0) return FFTH_OK;
+  if ((s = yzy<float>(P, d, nb, OP_GAMMA)) != FFTH_OK) return s;
+  {
+    ProfScope ps(P, C_XCG3, nb);
+    HIPCHK(Launch<float>::xcg3(P->n[2], P->iso, pv<float>(P, PS_XI), dim3(iblocks<float>(P), nb), P->stream, d,
+                               P->rows, P->nvox));
+  }
+  return fin(P, d, nb, FIN_CG3, 0, iblocks<float>(P));
 }
 
 // ---- autotuner ------------------------------------------------------------
@@ -391,7 +416,7 @@ template <class F> double time_launches(hipStream_t st, hipEvent_t e0, hipEvent_
   return ms / reps;
 }
 
-template <typename T> void tune_prec(ffth_plan* P, const Desc* d, int xf_mode, int xi_mode) {
+template <typename T> void tune_prec(ffth_plan* P, const Desc* d, int xf_mode, int xi_mode, bool fused) {
   const int pi = sizeof(T) == 8 ? 1 : 0;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return;
@@ -424,6 +449,10 @@ template <typename T> void tune_prec(ffth_plan* P, const Desc* d, int xf_mode, i
         t = time_launches(P->stream, e0, e1, [&] {
           (void)Launch<T>::zpass(P->n[0], v, dim3(nzb, 1), P->stream, d, OP_GAMMA, P->n[1], P->h,
                                  1.0 / (double)P->nvox);
+        });
+      } else if (fused) {
+        t = time_launches(P->stream, e0, e1, [&] {
+          (void)Launch<T>::xcg3(P->n[2], P->iso, v, dim3(iblocks<T>(P), 1), P->stream, d, P->rows, P->nvox);
         });
       } else {
         t = time_launches(P->stream, e0, e1, [&] {
@@ -468,8 +497,15 @@ ffth_status autotune(ffth_plan* P) {
     Desc d = base_desc(P, 0);
     d.st = P->d_state + 3 * P->nloads;
     int xf = XF_LS, xi = XI_BS;
+    bool fused = false;
     d.x = f32_ptr(P, 0, 0);
-    if (P->L.nf32 >= 3) {
+    if (mixed && P->L.nf32 == 4) {   // three-term CG inner solve
+      d.r = f32_ptr(P, 0, 1);
+      d.x1 = f32_ptr(P, 0, 2);
+      d.r1 = f32_ptr(P, 0, 3);
+      xf = XF_R3;
+      fused = true;
+    } else if (P->L.nf32 >= 3) {
       d.r = f32_ptr(P, 0, 1);
       d.p = f32_ptr(P, 0, 2);
       xf = XF_CG;
@@ -480,7 +516,7 @@ ffth_status autotune(ffth_plan* P) {
       xi = XI_BS_INNER;
     }
     if ((s = upload_one(d)) != FFTH_OK) return s;
-    tune_prec<float>(P, dd, xf, xi);
+    tune_prec<float>(P, dd, xf, xi, fused);
   }
   if (mixed || (o.precision == FFTH_FP64 && P->L.nf64 >= 2)) {   // FP64 passes
     Desc d = base_desc(P, 0);
@@ -499,7 +535,7 @@ ffth_status autotune(ffth_plan* P) {
       xi = XI_CG;
     }
     if ((s = upload_one(d)) != FFTH_OK) return s;
-    tune_prec<double>(P, dd, xf, xi);
+    tune_prec<double>(P, dd, xf, xi, false);
   }
   HIPCHK(hipStreamSynchronize(P->stream));
   HIPCHK(hipGetLastError());
@@ -598,6 +634,7 @@ struct Job {
   int sweeps = 0;       // FP64 residual sweeps done
   int inner_total = 0;  // FP32 inner iterations launched (budget: opts.max_iter)
   bool last = false;    // inner budget spent: the next sweep is the final one
+  bool fresh = false;   // inner solve entered: its three-term CG start pass is due
 };
 
 // Staging for combined descriptor arrays: 4 regions (one per phase kind) of
@@ -628,12 +665,11 @@ ffth_status stage_upload(ffth_plan* dims, Stage& st, int region, int count, cons
 ffth_status enter_inner(Job& J) {
   ffth_plan* P = J.P;
   const size_t bytes = (size_t)P->nvox * 6 * sizeof(float);
-  for (int l = 0; l < J.nl; ++l) {
-    if (P->opts.scheme == FFTH_CG) {
-      HIPCHK(hipMemsetAsync(f32_ptr(P, l, 0), 0, bytes, P->stream));  // delta = 0
-    } else {
+  if (P->opts.scheme == FFTH_CG) {
+    J.fresh = true;   // x_0 = 0 is implicit in the three-term CG
+  } else {
+    for (int l = 0; l < J.nl; ++l)   // Basic Scheme: x_0 = b
       HIPCHK(hipMemcpyAsync(f32_ptr(P, l, 0), f32_ptr(P, l, 1), bytes, hipMemcpyDeviceToDevice, P->stream));
-    }
   }
   J.phase = PH_INNER;
   return FFTH_OK;
@@ -646,17 +682,23 @@ ffth_status group_round(std::vector<Job*>& jobs, Stage& st) {
   ffth_plan* dims = jobs[0]->P;
   const ffth_opts& o = dims->opts;
   ffth_status s;
-  int nA0 = 0, nA = 0, nPR = 0, nIN = 0;
+  int nA0 = 0, nA = 0, nPR = 0, nIN = 0, nFresh = 0;
   int kin = o.check_every;
   for (Job* J : jobs) {
     switch (J->phase) {
       case PH_A0: nA0 = stage_append(st, 0, nA0, *J, R_MAIN, 0); break;
       case PH_A: nA = stage_append(st, 1, nA, *J, R_MAIN_DELTA, 0); break;
       case PH_PROJ: nPR = stage_append(st, 2, nPR, *J, R_PROJ, 0); break;
-      case PH_INNER:
-        nIN = stage_append(st, 3, nIN, *J, R_INNER, J->nl);
-        kin = std::min(kin, std::max(1, o.max_iter - J->inner_total));
-        break;
+      default: break;
+    }
+  }
+  // inner loads: those whose solve starts this round first (they take the start pass)
+  for (int pass = 0; pass < 2; ++pass) {
+    for (Job* J : jobs) {
+      if (J->phase != PH_INNER || J->fresh != (pass == 0)) continue;
+      nIN = stage_append(st, 3, nIN, *J, R_INNER, J->nl);
+      if (pass == 0) nFresh = nIN;
+      kin = std::min(kin, std::max(1, o.max_iter - J->inner_total));
     }
   }
   const Desc* d;
@@ -667,11 +709,13 @@ ffth_status group_round(std::vector<Job*>& jobs, Stage& st) {
   if ((s = stage_upload(dims, st, 2, nPR, &d)) != FFTH_OK) return s;
   if ((s = apply<float>(dims, d, nPR, XF_C0, OP_GAMMA, XI_PROJ, FIN_PROJ)) != FFTH_OK) return s;
   if ((s = stage_upload(dims, st, 3, nIN, &d)) != FFTH_OK) return s;
+  if (o.scheme == FFTH_CG && (s = cg3_start(dims, d, nFresh)) != FFTH_OK) return s;
   for (int j = 0; j < kin && nIN > 0; ++j) {
     if (o.scheme == FFTH_BASIC) s = apply<float>(dims, d, nIN, XF_MATVEC, OP_GAMMA, XI_BS_INNER, FIN_BS);
-    else s = apply<float>(dims, d, nIN, XF_CG, OP_GAMMA, XI_CG, FIN_CG_BETA);
+    else s = cg3_iter(dims, d, nIN);
     if (s != FFTH_OK) return s;
   }
+  for (Job* J : jobs) J->fresh = false;
   for (Job* J : jobs)
     HIPCHK(hipMemcpyAsync(J->P->h_state, J->P->d_state, J->P->L.nstate * sizeof(SolverState),
                           hipMemcpyDeviceToHost, dims->stream));
@@ -762,6 +806,7 @@ void build_solve_descs(ffth_plan* P, int nl, const double* E, double* eps, bool 
     if (o.precision == FFTH_MIXED) {
       // later sweeps: x += delta fused; full FP64 residual kept for its projection
       md.delta = f32_ptr(P, l, 0);
+      md.delta1 = o.scheme == FFTH_CG ? f32_ptr(P, l, 2) : nullptr;
       md.r = f64_ptr(P, l, 0);
       md.r_f32 = 0;
       pr.r = f64_ptr(P, l, 0);
@@ -772,9 +817,12 @@ void build_solve_descs(ffth_plan* P, int nl, const double* E, double* eps, bool 
     Desc in = base_desc(P, l);
     in.st = st_inner(P, l);
     if (o.precision == FFTH_MIXED) {
-      in.x = f32_ptr(P, l, 0);                                  // delta
-      in.r = f32_ptr(P, l, 1);                                  // inner residual / rhs
-      in.p = o.scheme == FFTH_CG ? f32_ptr(P, l, 2) : nullptr;  // CG direction
+      in.x = f32_ptr(P, l, 0);   // delta (slot 0)
+      in.r = f32_ptr(P, l, 1);   // inner residual / right-hand side (slot 0)
+      if (o.scheme == FFTH_CG) {
+        in.x1 = f32_ptr(P, l, 2);
+        in.r1 = f32_ptr(P, l, 3);
+      }
     }
     P->h_desc[desc_slot(P, R_INNER, l)] = in;
     Desc post = base_desc(P, l);
@@ -833,7 +881,7 @@ ffth_status solve_finish(ffth_plan* P, int nl, double* eps, ffth_result* res, do
     }
   const Desc* dp = dptr(P, R_POST);
   if (o.precision == FFTH_FP32) {
-    ProfScope ps(P, C_POINT);
+    ProfScope ps(P, C_POINT, nl);
     HIPCHK(launch_widen(nl, P->stream, dp, (long)P->nvox * 6));
   }
   // mean stress: the post descriptors read eps (FP64)
@@ -843,7 +891,7 @@ ffth_status solve_finish(ffth_plan* P, int nl, double* eps, ffth_result* res, do
   }
   const int nms = ms_blocks(P->nvox);
   {
-    ProfScope ps(P, C_POINT);
+    ProfScope ps(P, C_POINT, nl);
     HIPCHK(launch_mean_stress(P->iso, nms, nl, P->stream, dp, P->nvox));
   }
   if ((s = fin(P, dp, nl, FIN_SUMS_I, 0, nms)) != FFTH_OK) return s;
@@ -1115,7 +1163,7 @@ ffth_status build_order1_rhs(ffth_plan* P, int nl, const double* eps0, const dou
   if ((s = upload_states(P, post, 2 * P->nloads)) != FFTH_OK) return s;
   const int nms = ms_blocks(P->nvox);
   {
-    ProfScope ps(P, C_POINT);
+    ProfScope ps(P, C_POINT, nl);
     HIPCHK(launch_order1_point(P->iso, nms, nl, P->stream, dptr(P, R_POST), eps0, X1field(P), P->nvox));
   }
   if ((s = fin(P, dptr(P, R_POST), nl, FIN_O1RHS, 0, nms)) != FFTH_OK) return s;
@@ -1278,16 +1326,18 @@ ffth_status ffth_profile_enable(ffth_plan* P, int32_t on) {
   for (int c = 0; c < NCAT; ++c) {
     P->prof_ms[c] = 0.0;
     P->prof_n[c] = 0;
+    P->prof_units[c] = 0;
   }
   P->prof = on != 0;
   return FFTH_OK;
 }
 
-ffth_status ffth_profile_read(ffth_plan* P, int32_t category, int64_t* launches, double* ms) {
-  if (!P || category < 0 || category >= NCAT || !launches || !ms) return FFTH_ERR_INVALID;
+ffth_status ffth_profile_read(ffth_plan* P, int32_t category, int64_t* launches, int64_t* units, double* ms) {
+  if (!P || category < 0 || category >= NCAT || !launches || !units || !ms) return FFTH_ERR_INVALID;
   HIPCHK(hipStreamSynchronize(P->stream));
   prof_flush(P);
   *launches = P->prof_n[category];
+  *units = P->prof_units[category];
   *ms = P->prof_ms[category];
   return FFTH_OK;
 }
@@ -1332,6 +1382,7 @@ struct Request {
   std::vector<double> table;      // host copy of lame / stiffness
   std::vector<double> E;
   size_t off = 0, bytes = 0, ws_bytes = 0;
+  bool placed = false;            // [off, off + bytes) of the arena belongs to this request
   ffth_plan* P = nullptr;
   double* eps = nullptr;
   Job job;
@@ -1358,39 +1409,11 @@ struct ffth_server {
   ffth_opts opts{};
   int max_running = 0;
   Stage stage{nullptr, nullptr, 0};
-  std::map<size_t, size_t> free_;          // offset -> length of free arena ranges
+  FreeList free_;                          // free ranges of the arena
   std::deque<Request*> waiting;
   std::vector<Request*> running;
   std::map<uint64_t, Request*> reqs;
   uint64_t next = 1;
-
-  bool alloc(size_t need, size_t* off) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= need) {
-        *off = it->first;
-        const size_t rest = it->second - need, at = it->first + need;
-        free_.erase(it);
-        if (rest) free_[at] = rest;
-        return true;
-      }
-    }
-    return false;
-  }
-  void release(size_t off, size_t len) {
-    auto it = free_.emplace(off, len).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
 };
 
 namespace {
@@ -1400,8 +1423,9 @@ void finish_request(ffth_server* S, Request* r, ffth_status st) {
     (void)ffth_plan_destroy(r->P);
     r->P = nullptr;
   }
-  if (r->bytes) S->release(r->off, r->bytes);
-  r->bytes = 0;
+  // only memory the request was placed in goes back (a waiting request holds none)
+  if (r->placed && !S->free_.release(r->off, r->bytes)) g_last_error = "arena bookkeeping: overlapping release refused";
+  r->placed = false;
   r->status = st;
   r->state = st == FFTH_ERR_CANCELLED ? 3 : 2;
 }
@@ -1412,9 +1436,15 @@ ffth_status admit(ffth_server* S) {
   while (!S->waiting.empty() && (int)S->running.size() < S->max_running) {
     Request* r = S->waiting.front();
     size_t off;
-    if (!S->alloc(r->bytes, &off)) break;
+    if (!S->free_.alloc(r->bytes, &off)) break;
     S->waiting.pop_front();
+    const size_t stage_bytes = al((size_t)4 * S->stage.cap * sizeof(Desc));
+    if (off < stage_bytes || off + r->bytes > S->bytes) {   // never place over the staging area
+      finish_request(S, r, FFTH_ERR_OOM);
+      continue;
+    }
     r->off = off;
+    r->placed = true;
     r->prob.lame = r->iso ? r->table.data() : nullptr;
     r->prob.stiffness = r->iso ? nullptr : r->table.data();
     ffth_status st = ffth_plan_create(&r->P, &r->prob, &S->opts, r->nl, 0, S->arena + off, r->ws_bytes, S->stream);
@@ -1483,7 +1513,7 @@ ffth_status ffth_server_create(ffth_server** out, void* arena, size_t arena_byte
     delete S;
     return FFTH_ERR_DEVICE;
   }
-  S->free_[stage_bytes] = arena_bytes - stage_bytes;
+  S->free_.reset(stage_bytes, arena_bytes - stage_bytes);
   *out = S;
   return FFTH_OK;
 }

@@ -152,6 +152,58 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
   return x * q + (x < r ? x : r) + i;
 }
 
+// Rows of the x-passes sit in LDS as 3 complex sequences per row, each
+// packing two real components (c = 2q, 2q + 1) as real and imaginary part,
+// so that one complex FFT transforms two real rows.
+
+// After a forward FFT: unpack the two real transforms of each sequence and
+// store the half spectrum (k2 < N2/2) of the block's rows.
+template <typename T, int N2, int ROWS, int NTB>
+__device__ __forceinline__ void store_rows_r2c(C2<T>* spec, const C2<T>* z, long row0, long rows_total) {
+  constexpr int RS = N2 + N2 / 16;
+  constexpr int H = N2 / 2;
+  for (int v = threadIdx.x; v < ROWS * H * 6; v += NTB) {
+    const int rr = v / (H * 6), rem = v % (H * 6);
+    const long row = row0 + rr;
+    if (row >= rows_total) continue;
+    const int k = rem / 6, c = rem % 6, q = c >> 1;
+    const C2<T>* zr = z + (rr * 3 + q) * RS;
+    const C2<T> z1 = zr[padx<true>(k)];
+    const C2<T> z2 = conj(zr[padx<true>((N2 - k) % N2)]);
+    C2<T> o;
+    if ((c & 1) == 0) o = (z1 + z2) * T(0.5);
+    else o = C2<T>{(z1.y - z2.y) * T(0.5), -(z1.x - z2.x) * T(0.5)};
+    spec[spec_at(row, k, c, rows_total, kchunk(H))] = o;
+  }
+}
+
+// Before an inverse FFT: load the half spectrum of the block's rows and
+// rebuild the full Hermitian-packed sequences (Nyquist bin zero).
+template <typename T, int N2, int ROWS, int NTB>
+__device__ __forceinline__ void load_rows_c2r(const C2<T>* spec, C2<T>* z, long row0, long rows_total) {
+  constexpr int RS = N2 + N2 / 16;
+  constexpr int H = N2 / 2;
+  for (int v = threadIdx.x; v < ROWS * H * 3; v += NTB) {
+    const int rr = v / (H * 3), rem = v % (H * 3);
+    const int k = rem / 3, q = rem % 3;
+    const long row = row0 + rr;
+    C2<T> a = {0, 0}, b = {0, 0};
+    if (row < rows_total) {
+      const C2<T>* s = spec + spec_at(row, k, 2 * q, rows_total, kchunk(H));
+      a = s[0];
+      b = s[1];
+    }
+    C2<T>* zr = z + (rr * 3 + q) * RS;
+    if (k == 0) {
+      zr[padx<true>(0)] = C2<T>{a.x, b.x};
+      zr[padx<true>(H)] = C2<T>{0, 0};
+    } else {
+      zr[padx<true>(k)] = C2<T>{a.x - b.y, a.y + b.x};
+      zr[padx<true>(N2 - k)] = C2<T>{a.x + b.y, b.x - a.y};
+    }
+  }
+}
+
 template <typename T, int N2, bool ISO, int ROWS = x_rows<T>(N2), int NTB = NT>
 __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, int mode, long rows_total,
                                               long nvox) {
@@ -164,9 +216,16 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
   build_twiddles<T, N2, NTB>(tw);
   const long row0 = (long)blockIdx.x * ROWS;
   const T* mat = mat_of<T>(d);
-  double acc0 = 0.0;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
   const T beta = (T)d.st->beta;
   const bool first = d.st->first != 0;
+  // correction fused into the FP64 residual pass: with a three-term inner CG it
+  // sits in the slot of the inner iteration count's parity (none after 0 iterations)
+  const float* dl = d.delta;
+  if (d.delta1) {
+    const int it = d.st2->iters;
+    dl = it == 0 ? nullptr : (it & 1) ? d.delta1 : d.delta;
+  }
 
   for (int v = threadIdx.x; v < ROWS * N2; v += NTB) {
     const int rr = v / N2, i2 = v % N2;
@@ -181,10 +240,10 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
         if (xp) {
 #pragma unroll
           for (int c = 0; c < 6; ++c) x[c] = xp[c * nvox + vox];
-          if (d.delta) {
+          if (dl) {
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
-              x[c] += (T)d.delta[c * nvox + vox];
+              x[c] += (T)dl[c * nvox + vox];
               xp[c * nvox + vox] = x[c];
             }
           }
@@ -224,6 +283,22 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
         T cp[6];
         apply_mat<T, ISO>(mat, ph, false, p, cp);
         acc0 += (double)frob_w(p, cp);
+      } else if (mode == XF_R3) {
+        // start of the three-term CG: tau = (C - C0) r_0 and the sums
+        // <r, r>_C0, <r, C r> (= <r, A r>_C0 on compatible r) and ||r||^2
+        const T* rp = (const T*)((d.st->iters & 1) ? d.r1 : d.r);
+        T r[6], cr[6];
+        double rd[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          r[c] = rp[c * nvox + vox];
+          rd[c] = (double)r[c];
+        }
+        apply_mat<T, ISO>(mat, ph, true, r, tau);
+        apply_mat<T, ISO>(mat, ph, false, r, cr);
+        acc0 += c0_ip(d.lam0, d.mu0, rd, rd);
+        acc1 += (double)frob_w(r, cr);
+        acc2 += rd[0] * rd[0] + rd[1] * rd[1] + rd[2] * rd[2] + 2.0 * (rd[3] * rd[3] + rd[4] * rd[4] + rd[5] * rd[5]);
       } else if (mode == XF_C0) {
         // tau = C0 : r for the projection -Gamma0 * C0 r (r is the FP64 residual)
         const double* vp = (const double*)d.r;
@@ -246,22 +321,9 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
   __syncthreads();
   lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, -1>(z, tw);
 
-  C2<T>* spec = (C2<T>*)d.spec;
-  for (int v = threadIdx.x; v < ROWS * H * 6; v += NTB) {
-    const int rr = v / (H * 6), rem = v % (H * 6);
-    const long row = row0 + rr;
-    if (row >= rows_total) continue;
-    const int k = rem / 6, c = rem % 6, q = c >> 1;
-    const C2<T>* zr = z + (rr * 3 + q) * RS;
-    const C2<T> z1 = zr[padx<true>(k)];
-    const C2<T> z2 = conj(zr[padx<true>((N2 - k) % N2)]);
-    C2<T> o;
-    if ((c & 1) == 0) o = (z1 + z2) * T(0.5);
-    else o = C2<T>{(z1.y - z2.y) * T(0.5), -(z1.x - z2.x) * T(0.5)};
-    spec[spec_at(row, k, c, rows_total, kchunk(H))] = o;
-  }
-  double sums[1] = {acc0};
-  block_sums<1, NTB>(sums, d.part_f + blockIdx.x, gridDim.x);
+  store_rows_r2c<T, N2, ROWS, NTB>((C2<T>*)d.spec, z, row0, rows_total);
+  double sums[3] = {acc0, acc1, acc2};
+  block_sums<3, NTB>(sums, d.part_f + blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -277,27 +339,7 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
   if (!d.st->active) return;
   build_twiddles<T, N2, NTB>(tw);
   const long row0 = (long)blockIdx.x * ROWS;
-  const C2<T>* spec = (const C2<T>*)d.spec;
-
-  for (int v = threadIdx.x; v < ROWS * H * 3; v += NTB) {
-    const int rr = v / (H * 3), rem = v % (H * 3);
-    const int k = rem / 3, q = rem % 3;
-    const long row = row0 + rr;
-    C2<T> a = {0, 0}, b = {0, 0};
-    if (row < rows_total) {
-      const C2<T>* s = spec + spec_at(row, k, 2 * q, rows_total, kchunk(H));
-      a = s[0];
-      b = s[1];
-    }
-    C2<T>* zr = z + (rr * 3 + q) * RS;
-    if (k == 0) {
-      zr[padx<true>(0)] = C2<T>{a.x, b.x};
-      zr[padx<true>(H)] = C2<T>{0, 0};
-    } else {
-      zr[padx<true>(k)] = C2<T>{a.x - b.y, a.y + b.x};
-      zr[padx<true>(N2 - k)] = C2<T>{a.x + b.y, b.x - a.y};
-    }
-  }
+  load_rows_c2r<T, N2, ROWS, NTB>((const C2<T>*)d.spec, z, row0, rows_total);
   __syncthreads();
   lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, +1>(z, tw);
 
@@ -393,6 +435,93 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
   }
   double sums[2] = {acc0, acc1};
   block_sums<2, NTB>(sums, d.part_i + blockIdx.x, gridDim.x);
+}
+
+// ---------------------------------------------------------------------------
+// Three-term CG iteration fused into one x-pass: inverse FFT of eta_k =
+// -Gamma0 * (C - C0) r_k, the recurrences
+//   w = A r_k = r_k - eta_k
+//   r_{k+1} = omega (r_k - gamma w) + (1 - omega) r_{k-1}
+//   x_{k+1} = omega (x_k + gamma r_k) + (1 - omega) x_{k-1}
+// (gamma = <r,r>_C0 / <r,Ar>_C0, omega from the previous scalars; the first
+// step has omega = 1; x_0 = 0 is never stored), the sums of r_{k+1} and the forward FFT of
+// (C - C0) r_{k+1}, written back over the block's own spectrum rows.
+// Iterates ping-pong between two slots: r_k, x_k sit in slot (k & 1).
+// ---------------------------------------------------------------------------
+template <typename T, int N2, bool ISO, int ROWS = xi_rows<T>(N2), int NTB = NT>
+__global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, long rows_total, long nvox) {
+  constexpr int RS = N2 + N2 / 16;
+  __shared__ C2<T> z[ROWS * 3 * RS];
+  __shared__ C2<T> tw[N2];
+  const Desc& d = descs[blockIdx.y];
+  if (!d.st->active) return;
+  build_twiddles<T, N2, NTB>(tw);
+  const long row0 = (long)blockIdx.x * ROWS;
+  C2<T>* spec = (C2<T>*)d.spec;
+  load_rows_c2r<T, N2, ROWS, NTB>(spec, z, row0, rows_total);
+  __syncthreads();
+  lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, +1>(z, tw);
+
+  const int it = d.st->iters;
+  const bool first = d.st->first != 0;
+  const T gam = (T)d.st->alpha;
+  const T om = first ? T(1) : (T)d.st->beta;
+  const T* xc = (const T*)((it & 1) ? d.x1 : d.x);
+  const T* rc = (const T*)((it & 1) ? d.r1 : d.r);
+  T* xo = (T*)((it & 1) ? d.x : d.x1);
+  T* ro = (T*)((it & 1) ? d.r : d.r1);
+  const T* mat = mat_of<T>(d);
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+  for (int v = threadIdx.x; v < ROWS * N2; v += NTB) {
+    const int rr = v / N2, i2 = v % N2;
+    const long row = row0 + rr;
+    T tau[6] = {0, 0, 0, 0, 0, 0};
+    if (row < rows_total) {
+      const long vox = row * N2 + i2;
+      const int ph = d.phase[vox];
+      T rn[6];
+#pragma unroll
+      for (int q = 0; q < 3; ++q) {
+        const C2<T> e = z[(rr * 3 + q) * RS + padx<true>(i2)];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int c = 2 * q + h;
+          const T eta = h ? e.y : e.x;
+          const T r = rc[c * nvox + vox];
+          const T w = r - eta;
+          T xn, rv;
+          if (first) {
+            rv = r - gam * w;
+            xn = gam * r;
+          } else {
+            // x_{k-1} = x_0 = 0 at k = 1: its slot is never written in this solve
+            const T xold = it == 1 ? T(0) : xo[c * nvox + vox];
+            rv = om * (r - gam * w) + (T(1) - om) * ro[c * nvox + vox];
+            xn = om * (xc[c * nvox + vox] + gam * r) + (T(1) - om) * xold;
+          }
+          ro[c * nvox + vox] = rv;
+          xo[c * nvox + vox] = xn;
+          rn[c] = rv;
+        }
+      }
+      T cr[6];
+      double rd[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) rd[c] = (double)rn[c];
+      apply_mat<T, ISO>(mat, ph, true, rn, tau);
+      apply_mat<T, ISO>(mat, ph, false, rn, cr);
+      acc0 += c0_ip(d.lam0, d.mu0, rd, rd);
+      acc1 += (double)frob_w(rn, cr);
+      acc2 += rd[0] * rd[0] + rd[1] * rd[1] + rd[2] * rd[2] + 2.0 * (rd[3] * rd[3] + rd[4] * rd[4] + rd[5] * rd[5]);
+    }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) z[(rr * 3 + q) * RS + padx<true>(i2)] = C2<T>{tau[2 * q], tau[2 * q + 1]};
+  }
+  __syncthreads();
+  lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, -1>(z, tw);
+  store_rows_r2c<T, N2, ROWS, NTB>(spec, z, row0, rows_total);
+  double sums[3] = {acc0, acc1, acc2};
+  block_sums<3, NTB>(sums, d.part_i + blockIdx.x, gridDim.x);
 }
 
 // ---------------------------------------------------------------------------

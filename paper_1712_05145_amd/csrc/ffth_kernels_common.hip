@@ -30,6 +30,8 @@ __device__ static void fin_slots(int op, int& nf, int& ni) {
     case FIN_CG_BETA: ni = 2; break;
     case FIN_OUTER: case FIN_OUTER_P: nf = 1; ni = 2; break;
     case FIN_PROJ: ni = 2; break;
+    case FIN_CG3_INIT: nf = 3; break;
+    case FIN_CG3: ni = 3; break;
     case FIN_SUMS_I: case FIN_O1RHS: ni = NRED; break;
   }
 }
@@ -105,6 +107,42 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
       st->first = 0;
       fin_check(st);
       break;
+    case FIN_CG3_INIT: {
+      // three-term CG: rho_0 = <r,r>_C0, mu_0 = <r,Ar>_C0, gamma_0 = rho_0 / mu_0, omega_0 = 1
+      if (!(sf[1] > 0.0) || !(sf[0] > 0.0)) {
+        st->flag = sf[0] > 0.0 ? FLAG_DIVERGED : FLAG_CONVERGED;
+        st->active = 0;
+        break;
+      }
+      st->rr = sf[0];
+      st->alpha = sf[0] / sf[1];
+      st->beta = 1.0;
+      st->first = 1;
+      break;
+    }
+    case FIN_CG3: {
+      // si = (rho_{k+1}, mu_{k+1}, ||r_{k+1}||^2); state holds rho_k, gamma_k, omega_k
+      st->res = sqrt(si[2] / st->nb2);
+      st->iters++;
+      st->total++;
+      const double g = si[0] / si[1];
+      const double den = 1.0 - (g / st->alpha) * (si[0] / st->rr) / st->beta;
+      const double om = 1.0 / den;
+      st->first = 0;
+      if (st->res < st->tol) {
+        st->flag = FLAG_CONVERGED;
+        st->active = 0;
+      } else if (!(si[1] > 0.0) || !(om == om) || !(fabs(om) < 1e6)) {
+        st->flag = FLAG_DIVERGED;
+        st->active = 0;
+      } else {
+        st->rr = si[0];
+        st->alpha = g;
+        st->beta = om;
+        fin_check(st);
+      }
+      break;
+    }
     case FIN_PROJ: {
       // compatible part of the FP64 residual: restart the FP32 inner solve on it
       SolverState* in = d.st2;

@@ -51,6 +51,12 @@ static void xinv_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, 
   else hipLaunchKernelGGL((k_xinv<T, N, false, RW>), grid, dim3(NT), 0, s, d, mode, rows, nvox);
 }
 template <typename T, int N, int V>
+static void xcg3_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, long rows, long nvox) {
+  constexpr int RW = ffth::xi_rows_v<T>(N, V);
+  if (iso) hipLaunchKernelGGL((k_xcg3<T, N, true, RW>), grid, dim3(NT), 0, s, d, rows, nvox);
+  else hipLaunchKernelGGL((k_xcg3<T, N, false, RW>), grid, dim3(NT), 0, s, d, rows, nvox);
+}
+template <typename T, int N, int V>
 static void ypass_v(dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols, int ntiles) {
   constexpr int CW = ffth::y_cols_v<T>(N, V);
   constexpr int TB = ffth::y_threads_v<T>(N, V);
@@ -86,6 +92,18 @@ template <typename T> hipError_t Launch<T>::xinv(int n2, bool iso, int v, dim3 g
 #define FFTH_CASE(N)                                                          \
   if (n2 == N) {                                                              \
     FFTH_VARIANTS(xinv_v, N, iso, grid, s, d, mode, rows, nvox)              \
+    return hipGetLastError();                                                 \
+  }
+  FFTH_SIZES(FFTH_CASE)
+#undef FFTH_CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename T> hipError_t Launch<T>::xcg3(int n2, bool iso, int v, dim3 grid, hipStream_t s, const Desc* d,
+                                                long rows, long nvox) {
+#define FFTH_CASE(N)                                                          \
+  if (n2 == N) {                                                              \
+    FFTH_VARIANTS(xcg3_v, N, iso, grid, s, d, rows, nvox)                    \
     return hipGetLastError();                                                 \
   }
   FFTH_SIZES(FFTH_CASE)

@@ -11,7 +11,7 @@ struct SolverState {
   double tol;        // relative residual to reach
   double nb2;        // ||b||^2, the reference of the relative residual
   double rr;         // CG: <r, r>_C0
-  double alpha, beta;
+  double alpha, beta;  // CG: step and direction coefficients; three-term CG: gamma and omega
   double res;        // last relative residual
   double gscale;     // strain-like scale of the zero right-hand-side guard (<= 0: from ||P||)
   double guard_eps;  // relative threshold of the guard
@@ -39,6 +39,9 @@ struct Desc {
   void* r;                 // residual (compute precision, or FP32 when r_f32)
   void* p;                 // CG search direction
   float* delta;            // FP32 correction fused into the FP64 residual pass (or null)
+  float* delta1;           // its second slot when the inner solve is the three-term CG (or null)
+  void* x1;                // three-term CG: second iterate slot (x_{k-1}, overwritten by x_{k+1})
+  void* r1;                // three-term CG: second residual slot
   const double* P;         // stored right-hand-side polarization [6][N] (or null: C:E)
   void* io;                // generic input field (copy-in mode; order-1 p_2 output)
   void* out;               // generic output field (store / accumulate modes)
@@ -56,7 +59,7 @@ struct Desc {
 };
 
 // x-pass (forward) modes
-enum : int32_t { XF_LS = 0, XF_MATVEC = 1, XF_CG = 2, XF_COPY = 3, XF_C0 = 4 };
+enum : int32_t { XF_LS = 0, XF_MATVEC = 1, XF_CG = 2, XF_COPY = 3, XF_C0 = 4, XF_R3 = 5 };
 // x-pass (inverse) modes
 enum : int32_t { XI_STORE = 0, XI_ACCUM = 1, XI_BS = 2, XI_RESID = 3, XI_BS_INNER = 4, XI_CG = 5, XI_PROJ = 6 };
 // spectral operators of the z-pass
@@ -64,7 +67,7 @@ enum : int32_t { OP_GAMMA = 0, OP_THETA = 1, OP_DISP = 2 };
 // finalize operations
 enum : int32_t {
   FIN_LS_FIRST = 0, FIN_BS = 1, FIN_RESID_INIT = 2, FIN_CG_ALPHA = 3, FIN_CG_BETA = 4,
-  FIN_OUTER = 5, FIN_SUMS_I = 6, FIN_O1RHS = 7, FIN_OUTER_P = 8, FIN_PROJ = 9
+  FIN_OUTER = 5, FIN_SUMS_I = 6, FIN_O1RHS = 7, FIN_OUTER_P = 8, FIN_PROJ = 9, FIN_CG3_INIT = 10, FIN_CG3 = 11
 };
 
 constexpr int NRED = 8;   // doubles per block in the partial-sum arrays

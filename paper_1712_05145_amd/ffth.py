@@ -81,7 +81,8 @@ SIGNATURES = [
       ctypes.POINTER(ctypes.c_double)]),
     ("ffth_profile_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("ffth_profile_read", ctypes.c_int,
-     [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]),
+     [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+      ctypes.POINTER(ctypes.c_double)]),
     ("ffth_profile_name", ctypes.c_char_p, [ctypes.c_int32]),
     ("ffth_tile_variants", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     ("ffth_set_tile_variants", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
@@ -211,15 +212,20 @@ def ffth_profile_enable(plan, on=True):
     _check(load().ffth_profile_enable(plan, 1 if on else 0), "ffth_profile_enable")
 
 
+PROFILE_CATEGORIES = 11
+
+
 def ffth_profile_read(plan):
-    """{category name: (launches, total ms)} for every kernel category."""
+    """{category name: (launches, total ms, loads processed)} for every kernel category."""
     lib = load()
     out = {}
-    for c in range(10):
+    for c in range(PROFILE_CATEGORIES):
         n = ctypes.c_int64()
+        u = ctypes.c_int64()
         ms = ctypes.c_double()
-        _check(lib.ffth_profile_read(plan, c, ctypes.byref(n), ctypes.byref(ms)), "ffth_profile_read")
-        out[lib.ffth_profile_name(c).decode()] = (int(n.value), float(ms.value))
+        _check(lib.ffth_profile_read(plan, c, ctypes.byref(n), ctypes.byref(u), ctypes.byref(ms)),
+               "ffth_profile_read")
+        out[lib.ffth_profile_name(c).decode()] = (int(n.value), float(ms.value), int(u.value))
     return out
 
 

@@ -361,3 +361,19 @@ def test_autotuned_plan_matches_default_tiles():
         s.close()
     d = np.sqrt(np.outer(np.diag(out[False]), np.diag(out[False])))
     assert np.all(np.abs(out[True] - out[False]) <= 1e-8 * d)
+
+
+def test_mixed_three_term_inner_iterations_track_fp64_cg():
+    """The FP32 inner solves (three-term CG restarted after each FP64 sweep)
+    need about as many operator applications as plain FP64 CG."""
+    torch = require_gpu()
+    phase, lame = M.random_spheres(32, 6, seed=3)
+    lam0, mu0 = M.midpoint_reference(lame)
+    its = {}
+    for precision in ("fp64", "mixed"):
+        s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, precision=precision, tol=1e-8)
+        _, res = s.solve_order0(np.eye(6))
+        assert all(r["status"] == 0 and r["residual"] < 1e-8 for r in res)
+        its[precision] = sum(r["iters"] for r in res)
+    print("iterations", its)
+    assert its["mixed"] <= 1.3 * its["fp64"] + 12

@@ -78,7 +78,14 @@ def test_budget_admission_cancel_and_oversize():
     st, _ = srv.poll(ids[3])
     assert st == ffth.FFTH_ERR_CANCELLED
     done = _drain(srv, ids[:3])
-    assert all(done[i][0] == 0 for i in ids[:3])
+    assert all(done[i][0] == 0 for i in ids[:3]), [done[i][0] for i in ids[:3]]
+    # each request, run after a cancelled one in reused arena memory, equals the plan path
+    for r, rid in zip(reqs[:3], ids[:3]):
+        sol = ffth.Solver(r[0], r[2], r[3], lame=r[1], nloads=6, precision="mixed", tol=1e-8)
+        _, rp = sol.solve_order0(np.eye(6))
+        sol.close()
+        assert np.array_equal(np.array([x["mean_stress"] for x in rp]),
+                              np.array([x["mean_stress"] for x in done[rid][1]]))
     with pytest.raises(ffth.FFTHError) as e:       # larger than the whole arena
         srv.submit(*_req(128, 0.2, 20.0, 99), np.eye(6))
     assert e.value.status == ffth.FFTH_ERR_OOM

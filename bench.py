@@ -34,9 +34,15 @@ HBM_PEAK_GBS = 8000.0
 #   y-pass / z-pass        spectrum read and written                 24+24
 #   fused three-term CG    spectrum, r_k, x_k, r_k-1, x_k-1, phase read;
 #   x-pass                 r_k+1, x_k+1, spectrum written            24*5+2+24*3
-# (the FP32 x-forward / x-inverse categories mix the projection and start
-# passes, whose traffic differs by mode, and are reported without a model)
-ALG_BYTES_F32 = {"ypass_f32": 48.0, "zpass_f32": 48.0, "xcg3_f32": 194.0}
+#   start pass of a solve  r_0, phase read; spectrum written          24+2+24
+# The first iteration of each inner solve reads neither x_k nor r_k-1, x_k-1
+# (x_0 = 0, omega = 1) and the second does not read x_k-1: per started solve
+# the fused kernel moves 72 + 24 B/voxel less than 194 per iteration.  The
+# model subtracts both for every start (a lower bound on the bytes moved when
+# a solve stops after one iteration).  The FP32 x-forward / x-inverse
+# categories hold the projection passes only and are reported without a model.
+ALG_BYTES_F32 = {"ypass_f32": 48.0, "zpass_f32": 48.0, "xcg3_f32": 194.0, "cg3start_f32": 50.0}
+XCG3_START_SAVING = 96.0
 
 
 def measured_traffic(cat):
@@ -223,18 +229,32 @@ def main():
 
     inner = sum(r["iters"] for rs in results for r in rs)
     fp64_apps = sum(r["fp64_applications"] for rs in results for r in rs)
+    proj = sum(r["projections"] for rs in results for r in rs)
     bad = [r for rs in results for r in rs if r["status"] != 0]
     if bad:
         raise SystemExit(f"solve failed: {bad[0]}")
-    value = nvox * (inner + fp64_apps) / elapsed
+    value = nvox * (inner + proj + fp64_apps) / elapsed
     ms_step = elapsed / args.steps * 1e3
     ceff = np.array([r["mean_stress"] for r in results[-1][:6]]).T
 
-    # roofline of the dominant kernel; units = loads processed by its launches
+    # roofline of the dominant kernel.  Units = loads a category's launches
+    # really processed: a launch still carries loads that converged since the
+    # last read-back (their blocks exit at once), so the inner-loop kernels
+    # take their counts from the solver's own iteration counts instead.
     prof = {k: (prof0[k][0] + prof1[k][0], prof0[k][1] + prof1[k][1], prof0[k][2] + prof1[k][2]) for k in prof0}
+    starts = prof["cg3start_f32"][2]
+    real_units = {"xcg3_f32": inner, "ypass_f32": 2 * (inner + proj), "zpass_f32": inner + proj}
+    prof = {k: (v[0], v[1], real_units.get(k, v[2])) for k, v in prof.items()}
+
+    def alg_bytes(c, u):
+        b = ALG_BYTES_F32[c] * nvox * u
+        if c == "xcg3_f32":
+            b -= XCG3_START_SAVING * nvox * starts
+        return b
+
     cat = max(ALG_BYTES_F32, key=lambda c: prof[c][1])
     launches, tot_ms, units = prof[cat]
-    bytes_total = ALG_BYTES_F32[cat] * nvox * units
+    bytes_total = alg_bytes(cat, units)
     achieved = bytes_total / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
     kernels = {}
     for c in prof:
@@ -243,16 +263,17 @@ def main():
                  "avg_ms": round(ms / n_l, 4) if n_l else None,
                  "ms_per_load": round(ms / u, 4) if u else None}
         if c in ALG_BYTES_F32 and ms > 0:
-            entry["alg_bytes_per_voxel"] = ALG_BYTES_F32[c]
-            entry["achieved_GBs"] = round(ALG_BYTES_F32[c] * nvox * u / (ms * 1e-3) / 1e9, 1)
+            entry["alg_bytes_per_voxel_per_load"] = round(alg_bytes(c, u) / (nvox * u), 2)
+            entry["achieved_GBs"] = round(alg_bytes(c, u) / (ms * 1e-3) / 1e9, 1)
         kernels[c] = entry
     t_unit = measured_traffic(cat)
     upl = units / max(launches, 1)
     roofline = {"bound": "hbm", "kernel": cat, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if t_unit is None else round(t_unit * upl),
-                "traffic_per_load_launch": t_unit, "alg_bytes_per_load_launch": ALG_BYTES_F32[cat] * nvox,
-                "alg_bytes_per_voxel": ALG_BYTES_F32[cat], "units_per_launch": round(upl, 3),
+                "traffic_per_load_launch": t_unit, "alg_bytes_per_launch": round(bytes_total / max(launches, 1)),
+                "alg_bytes_per_voxel_per_load": round(bytes_total / (nvox * max(units, 1)), 2),
+                "units_per_launch": round(upl, 3),
                 "avg_launch_ms": round(tot_ms / max(launches, 1), 4),
                 "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 
@@ -263,8 +284,10 @@ def main():
         "config": {"workload": f"voronoi{args.n}-order0x6+order1", "grid": [args.n] * 3, "grains": args.grains,
                    "seed": args.seed, "scheme": args.scheme, "precision": "mixed", "tol": args.tol,
                    "loads_order0": 6, "loads_order1": 1, "parallelism": "single-gpu"},
-        "voxel_iters": {"fp32_inner": int(inner * nvox / args.steps), "fp64": int(fp64_apps * nvox / args.steps)},
-        "iters_per_step": {"fp32_inner": inner // args.steps, "fp64_applications": fp64_apps // args.steps},
+        "voxel_iters": {"fp32_inner": int(inner * nvox / args.steps), "fp32_projection": int(proj * nvox / args.steps),
+                        "fp64": int(fp64_apps * nvox / args.steps)},
+        "iters_per_step": {"fp32_inner": inner // args.steps, "fp32_projections": proj // args.steps,
+                           "fp64_applications": fp64_apps // args.steps},
         "latency_ms": {"p50": round(float(np.percentile(times, 50)) * 1e3, 2),
                        "p99": round(float(np.percentile(times, 99)) * 1e3, 2), "over": "timed steps"},
         "roofline": roofline,

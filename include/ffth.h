@@ -108,6 +108,9 @@ typedef struct {
                                  ones for MIXED)                                       */
   int32_t outer_iters;        /* MIXED: FP64 residual sweeps; else 0                    */
   int32_t fp64_applications;  /* FP64 operator applications (incl. the right-hand side) */
+  int32_t projections;        /* MIXED: FP32 compatible projections of the FP64 residual
+                                 (one FFT round trip each); else 0                       */
+  int32_t reserved;
   double residual;            /* final relative residual (FP64 true residual for MIXED) */
   double mean_stress[6];      /* order 0: Voigt <C:(E+eps)>; order 1: <C:eps + p_2>     */
   double g_mean[3];           /* order 1: the dropped mean <g> of the body force        */
@@ -179,9 +182,9 @@ ffth_status ffth_order1_rhs(ffth_plan *plan, const double *eps0_six, const doubl
 
 /* Kernel timing (diagnostics).  When enabled, every kernel launch of the plan
  * is bracketed by HIP events recorded on the plan's stream; the totals per
- * kernel category (0 .. 10: x-pass forward / y-pass / z-pass / x-pass inverse
+ * kernel category (0 .. 11: x-pass forward / y-pass / z-pass / x-pass inverse
  * in FP32, the same four in FP64, finalize, pointwise, fused three-term CG
- * x-pass) accumulate until the next ffth_profile_enable call, which also
+ * x-pass, its start pass) accumulate until the next ffth_profile_enable call, which also
  * resets them.  launches: kernel launches; units: batch entries (loads) they
  * processed, summed; ms: summed event time. */
 ffth_status ffth_profile_enable(ffth_plan *plan, int32_t on);
@@ -191,7 +194,7 @@ const char *ffth_profile_name(int32_t category);
 /* Tile variant chosen per pass: out[2*pass + prec], pass 0..3 = x-forward, y,
  * z, x-inverse; prec 0 = FP32, 1 = FP64 (variant 0 = the default shape). */
 ffth_status ffth_tile_variants(ffth_plan *plan, int32_t out[8]);
-/* Pin the tile variants (same layout; each in [0, 3)); results of every
+/* Pin the tile variants (same layout; each in [0, 4)); results of every
  * variant agree to rounding.  INVALID for a value out of range. */
 ffth_status ffth_set_tile_variants(ffth_plan *plan, const int32_t in[8]);
 

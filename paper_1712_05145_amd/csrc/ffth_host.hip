@@ -204,10 +204,10 @@ const Desc* dptr(ffth_plan* P, Role r) { return P->d_desc + desc_slot(P, r, 0); 
 int util6_slot(ffth_plan* P, int J) { return 7 * P->nloads + J; }
 
 // ---- kernel timing ---------------------------------------------------------
-enum Cat { C_XF32 = 0, C_Y32, C_Z32, C_XI32, C_XF64, C_Y64, C_Z64, C_XI64, C_FIN, C_POINT, C_XCG3, NCAT };
+enum Cat { C_XF32 = 0, C_Y32, C_Z32, C_XI32, C_XF64, C_Y64, C_Z64, C_XI64, C_FIN, C_POINT, C_XCG3, C_CG3S, NCAT };
 const char* const CAT_NAMES[NCAT] = {"xfwd_f32", "ypass_f32", "zpass_f32", "xinv_f32", "xfwd_f64",
                                      "ypass_f64", "zpass_f64", "xinv_f64", "finalize", "pointwise",
-                                     "xcg3_f32"};
+                                     "xcg3_f32", "cg3start_f32"};
 
 hipEvent_t take_event(ffth_plan* P) {
   if (P->pool.empty()) {
@@ -314,7 +314,7 @@ template <typename T> int xblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->nx6
 template <typename T> int iblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->ni64 : P->ni32; }
 
 template <typename T> ffth_status xfwd(ffth_plan* P, const Desc* d, int nb, int mode) {
-  ProfScope ps(P, sizeof(T) == 8 ? C_XF64 : C_XF32, nb);
+  ProfScope ps(P, sizeof(T) == 8 ? C_XF64 : mode == XF_R3 ? C_CG3S : C_XF32, nb);
   HIPCHK(Launch<T>::xfwd(P->n[2], P->iso, pv<T>(P, PS_XF), dim3(xblocks<T>(P), nb), P->stream, d, mode, P->rows,
                          P->nvox));
   return FFTH_OK;
@@ -912,6 +912,7 @@ ffth_status solve_finish(ffth_plan* P, int nl, double* eps, ffth_result* res, do
       r.iters = in.total;
       r.outer_iters = m.iters;
       r.fp64_applications = m.fp64_apps;
+      r.projections = m.proj;
     } else {
       r.iters = m.iters;
       r.fp64_applications = o.precision == FFTH_FP64 ? m.iters + (o.scheme == FFTH_CG ? 2 : 1) : 0;

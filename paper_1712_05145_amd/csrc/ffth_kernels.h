@@ -55,13 +55,15 @@ template <typename T> constexpr int z_cols(int n) {
 }
 // Candidate shapes for the runtime autotuner: variant 0 is the measured
 // default above, 1 and 2 halve / double the tile (or swap the block size of
-// the y-pass), within 96 KB of LDS per block.
+// the y-pass), within 96 KB of LDS per block; 3 keeps the tile of 0 with fewer
+// threads per block (x: one wave, z: two), for lengths whose Stockham stages
+// have fewer butterflies than the default block has threads.
 template <typename T> constexpr int lds_cap_rows(int n) {          // x-pass rows within 96 KB
   int r = 98304 / (3 * (n + n / 16) * (int)(2 * sizeof(T)));
   return r < 1 ? 1 : pow2_floor(r);
 }
 template <typename T> constexpr int var_rows(int r0, int n, int v) {
-  int r = v == 1 ? (r0 > 1 ? r0 / 2 : 1) : v == 2 ? 2 * r0 : r0;
+  int r = v == 1 ? (r0 > 1 ? r0 / 2 : 1) : v == 2 ? 2 * r0 : r0;   // v == 3: r0
   int c = lds_cap_rows<T>(n);
   return r > c ? c : r;
 }
@@ -72,6 +74,8 @@ template <typename T> constexpr int y_cols_v(int n, int v) {
   if (v == 2) c = c > 1 ? c / 2 : 1;
   return c;
 }
+template <typename T> constexpr int x_threads_v(int, int v) { return v == 3 ? 64 : NT; }
+template <typename T> constexpr int z_threads_v(int, int v) { return v == 3 ? 128 : NT; }
 template <typename T> constexpr int y_threads_v(int n, int v) {
   return v == 1 ? (y_threads<T>(n) == 512 ? 256 : 512) : v == 2 ? 256 : y_threads<T>(n);
 }

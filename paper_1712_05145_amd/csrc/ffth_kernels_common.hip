@@ -36,6 +36,19 @@ __device__ static void fin_slots(int op, int& nf, int& ni) {
   }
 }
 
+// This thread's share (i = threadIdx.x mod NT_FIN) of n partials, in a fixed
+// order, with 8 independent accumulators so that 8 loads are in flight.
+__device__ static double strided_sum(const double* __restrict__ p, int n) {
+  double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int i = threadIdx.x;
+  for (; i + 7 * NT_FIN < n; i += 8 * NT_FIN) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) a[u] += p[i + u * NT_FIN];
+  }
+  for (int u = 0; i < n; i += NT_FIN, ++u) a[u & 7] += p[i];
+  return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
 __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ descs, int op, int nblk_f, int nblk_i) {
   const Desc& d = descs[blockIdx.x];
   SolverState* st = d.st;
@@ -46,13 +59,8 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
   double af[NRED], ai[NRED];
 #pragma unroll
   for (int k = 0; k < NRED; ++k) {
-    double a = 0.0, b = 0.0;
-    if (k < nf)
-      for (int i = threadIdx.x; i < nblk_f; i += NT_FIN) a += d.part_f[(long)k * nblk_f + i];
-    if (k < ni)
-      for (int i = threadIdx.x; i < nblk_i; i += NT_FIN) b += d.part_i[(long)k * nblk_i + i];
-    af[k] = a;
-    ai[k] = b;
+    af[k] = k < nf ? strided_sum(d.part_f + (long)k * nblk_f, nblk_f) : 0.0;
+    ai[k] = k < ni ? strided_sum(d.part_i + (long)k * nblk_i, nblk_i) : 0.0;
   }
   block_sums<NRED, NT_FIN>(af, sf);
   block_sums<NRED, NT_FIN>(ai, si);
@@ -146,7 +154,7 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
     case FIN_PROJ: {
       // compatible part of the FP64 residual: restart the FP32 inner solve on it
       SolverState* in = d.st2;
-      st->fp64_apps++;
+      st->proj++;
       in->active = si[0] > 0.0 ? 1 : 0;
       in->nb2 = si[0];
       in->rr = si[1];

@@ -40,21 +40,21 @@ template <typename T> int Launch<T>::z_cols(int n, int v) {
 // one launcher per (length, variant): the tile shape is a template argument
 template <typename T, int N, int V>
 static void xfwd_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox) {
-  constexpr int RW = ffth::xf_rows_v<T>(N, V);
-  if (iso) hipLaunchKernelGGL((k_xfwd<T, N, true, RW>), grid, dim3(NT), 0, s, d, mode, rows, nvox);
-  else hipLaunchKernelGGL((k_xfwd<T, N, false, RW>), grid, dim3(NT), 0, s, d, mode, rows, nvox);
+  constexpr int RW = ffth::xf_rows_v<T>(N, V), TB = ffth::x_threads_v<T>(N, V);
+  if (iso) hipLaunchKernelGGL((k_xfwd<T, N, true, RW, TB>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
+  else hipLaunchKernelGGL((k_xfwd<T, N, false, RW, TB>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
 }
 template <typename T, int N, int V>
 static void xinv_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox) {
-  constexpr int RW = ffth::xi_rows_v<T>(N, V);
-  if (iso) hipLaunchKernelGGL((k_xinv<T, N, true, RW>), grid, dim3(NT), 0, s, d, mode, rows, nvox);
-  else hipLaunchKernelGGL((k_xinv<T, N, false, RW>), grid, dim3(NT), 0, s, d, mode, rows, nvox);
+  constexpr int RW = ffth::xi_rows_v<T>(N, V), TB = ffth::x_threads_v<T>(N, V);
+  if (iso) hipLaunchKernelGGL((k_xinv<T, N, true, RW, TB>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
+  else hipLaunchKernelGGL((k_xinv<T, N, false, RW, TB>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
 }
 template <typename T, int N, int V>
 static void xcg3_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, long rows, long nvox) {
-  constexpr int RW = ffth::xi_rows_v<T>(N, V);
-  if (iso) hipLaunchKernelGGL((k_xcg3<T, N, true, RW>), grid, dim3(NT), 0, s, d, rows, nvox);
-  else hipLaunchKernelGGL((k_xcg3<T, N, false, RW>), grid, dim3(NT), 0, s, d, rows, nvox);
+  constexpr int RW = ffth::xi_rows_v<T>(N, V), TB = ffth::x_threads_v<T>(N, V);
+  if (iso) hipLaunchKernelGGL((k_xcg3<T, N, true, RW, TB>), grid, dim3(TB), 0, s, d, rows, nvox);
+  else hipLaunchKernelGGL((k_xcg3<T, N, false, RW, TB>), grid, dim3(TB), 0, s, d, rows, nvox);
 }
 template <typename T, int N, int V>
 static void ypass_v(dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols, int ntiles) {
@@ -64,14 +64,15 @@ static void ypass_v(dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols,
 }
 template <typename T, int N, int V>
 static void zpass_v(dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h, double scale) {
-  constexpr int TK = ffth::z_cols_v<T>(N, V);
-  hipLaunchKernelGGL((k_zpass<T, N, TK>), grid, dim3(NT), 0, s, d, op, n1, h, scale);
+  constexpr int TK = ffth::z_cols_v<T>(N, V), TB = ffth::z_threads_v<T>(N, V);
+  hipLaunchKernelGGL((k_zpass<T, N, TK, TB>), grid, dim3(TB), 0, s, d, op, n1, h, scale);
 }
 
 #define FFTH_VARIANTS(F, N, ...)          \
   switch (v) {                            \
     case 1: F<T, N, 1>(__VA_ARGS__); break; \
     case 2: F<T, N, 2>(__VA_ARGS__); break; \
+    case 3: F<T, N, 3>(__VA_ARGS__); break; \
     default: F<T, N, 0>(__VA_ARGS__);     \
   }
 

@@ -23,7 +23,7 @@ struct SolverState {
   int32_t first;     // CG: the next direction update takes p = r
   int32_t max_iter;  // stop (unconverged) after this many iterations
   int32_t fp64_apps; // FP64 operator applications (outer state only)
-  int32_t pad;
+  int32_t proj;      // FP32 projection passes (outer state only)
 };
 
 enum : int32_t { FLAG_RUNNING = 0, FLAG_CONVERGED = 1, FLAG_DIVERGED = 2, FLAG_ZERO_RHS = 3 };
@@ -71,6 +71,6 @@ enum : int32_t {
 };
 
 constexpr int NRED = 8;   // doubles per block in the partial-sum arrays
-constexpr int NVAR = 3;   // compiled tile shapes per pass (autotuner candidates)
+constexpr int NVAR = 4;   // compiled tile shapes per pass (autotuner candidates)
 
 }  // namespace ffth

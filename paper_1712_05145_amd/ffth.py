@@ -46,13 +46,15 @@ class ffth_opts(ctypes.Structure):
 
 class ffth_result(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("iters", ctypes.c_int32), ("outer_iters", ctypes.c_int32),
-                ("fp64_applications", ctypes.c_int32), ("residual", ctypes.c_double),
+                ("fp64_applications", ctypes.c_int32), ("projections", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("residual", ctypes.c_double),
                 ("mean_stress", ctypes.c_double * 6), ("g_mean", ctypes.c_double * 3),
                 ("seconds", ctypes.c_double)]
 
     def as_dict(self):
         return {"status": self.status, "iters": self.iters, "outer_iters": self.outer_iters,
-                "fp64_applications": self.fp64_applications, "residual": self.residual,
+                "fp64_applications": self.fp64_applications, "projections": self.projections,
+                "residual": self.residual,
                 "mean_stress": list(self.mean_stress), "g_mean": list(self.g_mean), "seconds": self.seconds}
 
 
@@ -212,7 +214,7 @@ def ffth_profile_enable(plan, on=True):
     _check(load().ffth_profile_enable(plan, 1 if on else 0), "ffth_profile_enable")
 
 
-PROFILE_CATEGORIES = 11
+PROFILE_CATEGORIES = 12
 
 
 def ffth_profile_read(plan):

@@ -105,7 +105,8 @@ def replay(server, stream, inputs, loads=None, time_scale=1.0, on_done=None):
             req, arr, nvox = inflight.pop(rid)
             rec = {"id": req["id"], "n": req.get("n"), "status": st, "arrival": arr, "done": tnow,
                    "latency": tnow - arr, "results": res,
-                   "voxel_iters": nvox * sum(r["iters"] + r["fp64_applications"] for r in res) if res else 0}
+                   "voxel_iters": nvox * sum(r["iters"] + r["projections"] + r["fp64_applications"] for r in res)
+                   if res else 0}
             records.append(rec)
             if on_done:
                 on_done(rec)

@@ -21,7 +21,7 @@
  * Conventions (fixed by this library where the paper is silent):
  *   grid      n[3] voxels, C order, grid axis d carries x_{d+1}; voxel centres
  *             -1/2 + (j + 1/2)/n_d; every n_d even and in the supported set
- *             (ffth_size_supported).
+ *             (ffth_size_supported), except n0 = 1 (2-D problems, Sec. 4).
  *   fields    strain-like fields are 6 tensor components per voxel in the
  *             order (11, 22, 33, 23, 13, 12), stored component-major:
  *             field[c * N + voxel], N = n0*n1*n2.
@@ -123,7 +123,10 @@ typedef struct ffth_plan ffth_plan;
  * max_outer 30, check_every 8, autotune 1. */
 void ffth_default_opts(ffth_opts *o);
 
-/* 1 if n (one axis length) is supported by the compiled FFT kernels. */
+/* 1 if n (one axis length) is supported by the compiled FFT kernels
+ * (4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512, 1024).  Axis 0 may
+ * also have length 1: a 2-D problem in the (x2, x3) plane (every field
+ * invariant along x1; with plane-stress moduli the plane-stress problem). */
 int32_t ffth_size_supported(int32_t n);
 
 /* Bytes of caller-owned device workspace needed by a plan for grids of size

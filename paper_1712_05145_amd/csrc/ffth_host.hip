@@ -962,10 +962,8 @@ int32_t ffth_size_supported(int32_t n) { return size_supported(n) ? 1 : 0; }
 
 size_t ffth_workspace_bytes(const int32_t n[3], int32_t nphases, int32_t nloads, int32_t order, const ffth_opts* o) {
   if (!n || !o || nloads < 1 || nphases < 1 || nphases > 65535 || (order != 0 && order != 1)) return 0;
-  for (int d = 0; d < 3; ++d)
-    if (!size_supported(n[d])) return 0;
-  if (!opts_valid(*o)) return 0;
   int nn[3] = {n[0], n[1], n[2]};
+  if (!grid_supported(nn) || !opts_valid(*o)) return 0;
   return make_layout(nn, nphases, nloads, order, *o).total;
 }
 
@@ -997,11 +995,14 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
     g_last_error = "workspace not 256-byte aligned";
     return FFTH_ERR_INVALID;
   }
-  for (int d = 0; d < 3; ++d)
-    if (!size_supported(p->n[d])) {
-      g_last_error = "unsupported grid size " + std::to_string(p->n[d]);
+  {
+    int nn[3] = {p->n[0], p->n[1], p->n[2]};
+    if (!grid_supported(nn)) {
+      g_last_error = "unsupported grid " + std::to_string(nn[0]) + "x" + std::to_string(nn[1]) + "x" +
+                     std::to_string(nn[2]);
       return FFTH_ERR_INVALID;
     }
+  }
   if (p->nphases < 1 || p->nphases > 65535 || !p->phase || ((p->lame == nullptr) == (p->stiffness == nullptr))) {
     g_last_error = "bad phase table";
     return FFTH_ERR_INVALID;
@@ -1476,10 +1477,8 @@ extern "C" {
 
 size_t ffth_request_bytes(const int32_t n[3], int32_t nphases, int32_t nloads, const ffth_opts* o) {
   if (!n || !o || nloads < 1 || nphases < 1 || nphases > 65535) return 0;
-  for (int d = 0; d < 3; ++d)
-    if (!size_supported(n[d])) return 0;
-  if (!opts_valid(*o)) return 0;
   int nn[3] = {n[0], n[1], n[2]};
+  if (!grid_supported(nn) || !opts_valid(*o)) return 0;
   return request_bytes(nn, nphases, nloads, *o, nullptr);
 }
 
@@ -1525,11 +1524,13 @@ ffth_status ffth_submit(ffth_server* S, const ffth_problem* p, int32_t nloads, c
     g_last_error = "bad argument (1..6 load cases per request)";
     return FFTH_ERR_INVALID;
   }
-  for (int d = 0; d < 3; ++d)
-    if (!size_supported(p->n[d])) {
+  {
+    int nn[3] = {p->n[0], p->n[1], p->n[2]};
+    if (!grid_supported(nn)) {
       g_last_error = "unsupported grid size";
       return FFTH_ERR_INVALID;
     }
+  }
   if (p->nphases < 1 || p->nphases > 65535 || !p->phase || ((p->lame == nullptr) == (p->stiffness == nullptr))) {
     g_last_error = "bad phase table";
     return FFTH_ERR_INVALID;

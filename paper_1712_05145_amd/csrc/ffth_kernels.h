@@ -674,7 +674,7 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
     store_v<T, V>(buf + i0 * W + w, a);
   }
   __syncthreads();
-  lds_fft<T, N0, W, NTB, W, 1, true, false, -1, V>(buf, tw);
+  if constexpr (N0 > 1) lds_fft<T, N0, W, NTB, W, 1, true, false, -1, V>(buf, tw);
   for (int v = threadIdx.x; v < N0 * TK; v += NTB) {
     const int k0 = v / TK, col = v % TK;
     const long m = m0 + col;
@@ -710,7 +710,7 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
     }
   }
   __syncthreads();
-  lds_fft<T, N0, W, NTB, W, 1, true, false, +1, V>(buf, tw);
+  if constexpr (N0 > 1) lds_fft<T, N0, W, NTB, W, 1, true, false, +1, V>(buf, tw);
   for (int v = threadIdx.x; v < N0 * W / V; v += NTB) {
     const int i0 = v / (W / V), w = (v % (W / V)) * V;
     if (m0 + w / 6 < M) {

@@ -320,6 +320,10 @@ bool size_supported(int n) {
   return false;
 }
 
+bool grid_supported(const int n[3]) {
+  return (n[0] == 1 || size_supported(n[0])) && size_supported(n[1]) && size_supported(n[2]);
+}
+
 hipError_t launch_finalize(int nbatch, hipStream_t s, const Desc* d, int op, int nblk_f, int nblk_i) {
   hipLaunchKernelGGL(k_finalize, dim3(nbatch), dim3(NT_FIN), 0, s, d, op, nblk_f, nblk_i);
   return hipGetLastError();

@@ -32,7 +32,7 @@ template <typename T> int Launch<T>::y_cols(int n, int v) {
 }
 template <typename T> int Launch<T>::z_cols(int n, int v) {
 #define FFTH_CASE(N) if (n == N) return ffth::z_cols_v<T>(N, v);
-  FFTH_SIZES(FFTH_CASE)
+  FFTH_ZSIZES(FFTH_CASE)
 #undef FFTH_CASE
   return 0;
 }
@@ -131,7 +131,7 @@ template <typename T> hipError_t Launch<T>::zpass(int n0, int v, dim3 grid, hipS
     FFTH_VARIANTS(zpass_v, N, grid, s, d, op, n1, h, scale)                  \
     return hipGetLastError();                                                 \
   }
-  FFTH_SIZES(FFTH_CASE)
+  FFTH_ZSIZES(FFTH_CASE)
 #undef FFTH_CASE
   return hipErrorInvalidValue;
 }

@@ -5,11 +5,16 @@
 #include "ffth_types.h"
 
 // Axis lengths with compiled FFT kernels.
-#define FFTH_SIZES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256) X(512)
+#define FFTH_SIZES(X) X(4) X(6) X(8) X(12) X(16) X(24) X(32) X(48) X(64) X(96) X(128) X(256) X(512) X(1024)
+// Axis 0 may also have length 1: a 2-D problem in the (x2, x3) plane, whose
+// z-pass applies the spectral operator without a transform.
+#define FFTH_ZSIZES(X) X(1) FFTH_SIZES(X)
 
 namespace ffth {
 
 bool size_supported(int n);
+// every axis length supported (axis 0 may be 1)
+bool grid_supported(const int n[3]);
 
 // Every pass has NVAR compiled tile shapes (variant v); the plan picks one
 // per pass and precision (autotuned or the default 0).

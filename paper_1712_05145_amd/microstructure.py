@@ -191,6 +191,39 @@ def coated_sphere(n, r1=0.25, r2=0.4):
     return phase
 
 
+def plane_stress_lame(lame):
+    """(lambda, mu) rows -> plane-stress in-plane moduli (2 lam mu / (lam + 2 mu), mu)."""
+    lame = np.asarray(lame, dtype=np.float64)
+    lam, mu = lame[:, 0], lame[:, 1]
+    return np.stack([2.0 * lam * mu / (lam + 2.0 * mu), mu], axis=1)
+
+
+def hashin_2d(n, r1=0.25, r2=0.4, young=(100.0, 1000.0, 453.685), nu=0.3):
+    """Hashin's coated circular inclusion of Sec. 4 on a (1, n, n) grid: the
+    plane is (x2, x3), every field is invariant along x1.  Phases: 0 core
+    (radius r1), 1 coating (radius r2), 2 matrix; plane-stress moduli.  The
+    default moduli are the paper's, with the matrix modulus that makes the
+    coated inclusion neutral."""
+    y = voxel_centres(n)
+    d = np.sqrt(y[:, None] ** 2 + y[None, :] ** 2)
+    plane = np.full((n, n), 2, dtype=np.uint16)
+    plane[d < r2] = 1
+    plane[d < r1] = 0
+    lame = plane_stress_lame(lame_from_young(np.asarray(young, float), [nu] * len(young)))
+    return plane[None, :, :], lame
+
+
+def hashin_2d_contrast(n, contrast, r1=0.25, r2=0.4, nu=0.3):
+    """The same geometry with core E = 1, coating E = contrast and the neutral
+    matrix modulus for that pair (2-D neutral-coating condition, plane stress)."""
+    e1, e2 = 1.0, float(contrast)
+    k1, k2 = e1 / (2 * (1 - nu)), e2 / (2 * (1 - nu))
+    mu2 = e2 / (2 * (1 + nu))
+    f = (r1 / r2) ** 2
+    k3 = k2 + f / (1.0 / (k1 - k2) + (1 - f) / (k2 + mu2)) if e1 != e2 else k1
+    return hashin_2d(n, r1, r2, young=(e1, e2, 2 * k3 * (1 - nu)), nu=nu)
+
+
 def random_phases(n, nphases, seed):
     """Independent random phase per voxel (worst case for the constitutive law)."""
     if np.isscalar(n):

@@ -28,13 +28,17 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_supported_sizes_and_workspace():
-    for n in (4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512):
+    for n in (4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512, 1024):
         assert ffth.ffth_size_supported(n)
-    for n in (0, 1, 2, 3, 5, 7, 10, 1024):
+    for n in (0, 1, 2, 3, 5, 7, 10, 2048):
         assert not ffth.ffth_size_supported(n)
     o = ffth.make_opts()
     assert ffth.ffth_workspace_bytes((16, 16, 16), 2, 1, 0, o) > 0
     assert ffth.ffth_workspace_bytes((16, 16, 10), 2, 1, 0, o) == 0
+    # 2-D problems: only the first axis may have length 1
+    assert ffth.ffth_workspace_bytes((1, 16, 16), 2, 1, 0, o) > 0
+    assert ffth.ffth_workspace_bytes((16, 1, 16), 2, 1, 0, o) == 0
+    assert ffth.ffth_workspace_bytes((16, 16, 1), 2, 1, 0, o) == 0
     assert ffth.ffth_workspace_bytes((16, 16, 16), 0, 1, 0, o) == 0
     # more loads, order 1 and FP64 CG all need more workspace
     b1 = ffth.ffth_workspace_bytes((32, 32, 32), 2, 1, 0, o)

@@ -14,7 +14,7 @@ from tests._gpu import full, rel_l2, require_gpu, to_dev, voigt6
 
 pytestmark = pytest.mark.gpu
 
-SIZES = [4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512]
+SIZES = [4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512, 1024]
 # every size in every axis position, with small companions
 SHAPES = sorted({s for n in SIZES for s in [(n, 6, 8), (8, n, 6), (6, 8, n)]})
 

@@ -235,3 +235,21 @@ def test_iteration_counts_soft():
     assert its[(16, "cg")] < its[(16, "basic")] / 3
     assert 0.5 < its[(16, "cg")] / its[(8, "cg")] < 2.0
     assert 0.5 < its[(16, "basic")] / its[(8, "basic")] < 2.0
+
+
+def test_hashin_2d_orientation_and_generator():
+    """The GPU's 2-D layout (1, n, n) (plane x2-x3) gives the oracle the same
+    in-plane bulk response as the (n, n, 1) layout of the neutrality test."""
+    phase, lame = M.hashin_2d(16)
+    assert phase.shape == (1, 16, 16)
+    lam0, mu0 = M.midpoint_reference(lame)
+    a = H.make_problem(phase, lam0, mu0, lame=lame)
+    b = H.make_problem(np.ascontiguousarray(np.transpose(phase, (1, 2, 0))), lam0, mu0, lame=lame)
+    _, ma, _ = H.solve_order0(a, [0, 1, 1, 0, 0, 0], "cg", tol=1e-12)
+    _, mb, _ = H.solve_order0(b, [1, 1, 0, 0, 0, 0], "cg", tol=1e-12)
+    assert abs((ma[1] + ma[2]) - (mb[0] + mb[1])) < 1e-10 * abs(mb[0] + mb[1])
+    # the neutral matrix modulus of the contrast generator (core E = 1, coating
+    # E = 10) is the paper's printed value scaled by its core modulus 100
+    lam, mu = M.hashin_2d_contrast(8, 10.0)[1][2]
+    young3 = 4 * mu * (lam + mu) / (lam + 2 * mu)       # plane-stress E from (lam_ps, mu)
+    assert abs(young3 * 100 - 453.685) < 5e-3

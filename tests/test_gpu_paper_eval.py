@@ -108,3 +108,27 @@ def test_hashin2d_neutral_inclusion_large_grids():
     print("neutrality errors", errs)
     assert errs[0] < 0.02 * 32 / 128
     assert errs[2] < errs[0]
+
+
+def test_coated_sphere_3d_neutral_inclusion():
+    """3-D analogue of Sec. 4's structure: a coated sphere with the neutral
+    matrix bulk modulus leaves the cell's bulk modulus at the matrix value."""
+    torch = require_gpu()
+    errs = []
+    for n in (64, 128):
+        print("case coated sphere", n, flush=True)
+        young = np.array([100.0, 1000.0])
+        lame = M.lame_from_young(young, [0.3, 0.3])
+        k = lame[:, 0] + 2 * lame[:, 1] / 3
+        f = (0.25 / 0.4) ** 3
+        k3 = k[1] + f / (1 / (k[0] - k[1]) + 3 * (1 - f) / (3 * k[1] + 4 * lame[1, 1]))
+        lame = np.vstack([lame, M.lame_from_young([3 * k3 * (1 - 2 * 0.3)], [0.3])])
+        phase = M.coated_sphere(n)
+        lam0, mu0 = M.midpoint_reference(lame)
+        s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=1, precision="mixed", tol=1e-8)
+        _, res = s.solve_order0([1, 1, 1, 0, 0, 0])
+        s.close()
+        k_eff = sum(res[0]["mean_stress"][:3]) / 9.0
+        errs.append(abs(k_eff / k3 - 1))
+    print("coated sphere neutrality errors", errs)
+    assert max(errs) < 0.01

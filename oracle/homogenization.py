@@ -36,6 +36,8 @@ def _solve(prob, p_rhs, scheme, tol, max_iter, scale):
         eps, info = solvers.basic_scheme(prob, b, tol, max_iter, scale=scale)
     elif scheme == "cg":
         eps, info = solvers.conjugate_gradient(prob, b, tol, max_iter, scale=scale)
+    elif scheme == "bicgstab":
+        eps, info = solvers.bicgstab(prob, b, tol, max_iter, scale=scale)
     else:
         raise ValueError(scheme)
     info["b_norm"] = tensors.l2norm(b)

@@ -25,7 +25,7 @@ def test_dense_galerkin_equals_iterative_solutions(n, seed):
     _, _, prob = _two_phase_problem(n, seed)
     e = np.array([1.0, -0.3, 0.2, 0.4, 0.0, 0.5])
     ref = solvers.dense_galerkin(prob.C, e_macro=tensors.tensor_from_engineering(e))
-    for scheme in ("basic", "cg"):
+    for scheme in ("basic", "cg", "bicgstab"):
         eps, _, info = H.solve_order0(prob, e, scheme, tol=1e-13)
         assert info["converged"]
         assert np.abs(eps - ref).max() < 1e-11 * np.abs(ref).max()
@@ -253,3 +253,40 @@ def test_hashin_2d_orientation_and_generator():
     lam, mu = M.hashin_2d_contrast(8, 10.0)[1][2]
     young3 = 4 * mu * (lam + mu) / (lam + 2 * mu)       # plane-stress E from (lam_ps, mu)
     assert abs(young3 * 100 - 453.685) < 5e-3
+
+
+def test_bicgstab_follows_scipy_bicgstab():
+    """The oracle's BiCGSTAB takes the iterates of scipy's independent
+    implementation of the same method (same start, shadow residual r_0,
+    Euclidean product of the full 3x3 tensor field): same solution and the
+    same iteration count to the same tolerance; its residual is the true one."""
+    from scipy.sparse.linalg import LinearOperator, bicgstab as sp_bicgstab
+    phase, lame, prob = _two_phase_problem(6, 4, young=(1.0, 30.0))
+    e = np.array([1.0, 0.0, 0.0, 0.0, 0.0, 0.0])
+    b = prob.rhs(prob.C.contract_const(tensors.tensor_from_engineering(e)))
+    shape = b.shape
+    tol = 1e-9
+    eps, info = solvers.bicgstab(prob, b, tol)
+    op = LinearOperator((b.size, b.size), matvec=lambda v: prob.apply_A(v.reshape(shape)).ravel(), dtype=float)
+    its = []
+    x_sp, code = sp_bicgstab(op, b.ravel(), x0=b.ravel().copy(), rtol=tol, atol=0.0,
+                             callback=lambda xk: its.append(1))
+    assert code == 0 and info["converged"]
+    assert abs(info["iters"] - len(its)) <= 1
+    assert np.abs(eps.ravel() - x_sp).max() < 1e-6 * np.abs(x_sp).max()
+    assert solvers.true_residual(prob, eps, b) < 10 * tol
+    # and the same discrete solution as CG
+    eps_cg, _ = solvers.conjugate_gradient(prob, b, 1e-12)
+    assert np.abs(eps - eps_cg).max() < 1e-7 * np.abs(eps_cg).max()
+
+
+def test_bicgstab_zero_and_trivial_cases():
+    """C = C0: A = Id, x_0 = b is exact (0 iterations); zero right-hand side -> 0."""
+    phase = M.random_phases(4, 2, 1)
+    lame = np.array([[2.0, 1.0], [2.0, 1.0]])
+    prob = H.make_problem(phase, 2.0, 1.0, lame=lame)
+    eps, _, info = H.solve_order0(prob, [1, 0, 0, 0, 0, 0], "bicgstab", tol=1e-12)
+    assert info["iters"] == 0 and np.abs(eps).max() < 1e-15
+    _, _, prob2 = _two_phase_problem(4, 3)
+    eps, _, info = H.solve_order0(prob2, [0, 0, 0, 0, 0, 0], "bicgstab", tol=1e-12)
+    assert info["iters"] == 0 and np.abs(eps).max() == 0.0

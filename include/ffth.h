@@ -69,7 +69,9 @@ typedef enum {
   FFTH_ERR_CANCELLED = 7       /* request cancelled (serving)                       */
 } ffth_status;
 
-typedef enum { FFTH_BASIC = 0, FFTH_CG = 1 } ffth_scheme;
+/* FFTH_BICGSTAB: BiCGSTAB on eq. (6), the Krylov method of the paper's
+ * experiments (Sec. 4); FP64 or FP32 precision only. */
+typedef enum { FFTH_BASIC = 0, FFTH_CG = 1, FFTH_BICGSTAB = 2 } ffth_scheme;
 typedef enum { FFTH_FP64 = 0, FFTH_FP32 = 1, FFTH_MIXED = 2 } ffth_precision;
 
 /* The cell problem of Sec. 2: stiffness field C(x) = table[phase[x]] with

@@ -74,9 +74,9 @@ Layout make_layout(const int n[3], int nph, int nloads, int order, const ffth_op
   L.nstate = 3 * nloads + 1;
   L.nblk = std::max((int)((long)n[0] * n[1]), ms_blocks(nvox));   // x-pass blocks of any variant (>= 1 row)
   // per-load FP32 / FP64 field counts
-  if (prec == FFTH_FP32) L.nf32 = scheme == FFTH_CG ? 3 : 1;
+  if (prec == FFTH_FP32) L.nf32 = scheme == FFTH_CG ? 3 : scheme == FFTH_BICGSTAB ? 7 : 1;
   if (prec == FFTH_MIXED) L.nf32 = scheme == FFTH_CG ? 4 : 2;   // three-term CG: x, r in two slots each
-  if (prec == FFTH_FP64) L.nf64 = scheme == FFTH_CG ? 2 : 0;
+  if (prec == FFTH_FP64) L.nf64 = scheme == FFTH_CG ? 2 : scheme == FFTH_BICGSTAB ? 6 : 0;
   if (prec == FFTH_MIXED) L.nf64 = 1;   // FP64 residual before its compatible projection
   L.spec_stride = al((size_t)nvox * 6 * sizeof(double));     // 6 x (nvox/2) complex FP64
   L.f32_stride = al((size_t)nvox * 6 * sizeof(float));
@@ -104,7 +104,8 @@ Layout make_layout(const int n[3], int nph, int nloads, int order, const ffth_op
 }
 
 bool opts_valid(const ffth_opts& o) {
-  if (o.scheme != FFTH_BASIC && o.scheme != FFTH_CG) return false;
+  if (o.scheme != FFTH_BASIC && o.scheme != FFTH_CG && o.scheme != FFTH_BICGSTAB) return false;
+  if (o.scheme == FFTH_BICGSTAB && o.precision == FFTH_MIXED) return false;   // FP64 or FP32 only
   if (o.precision < FFTH_FP64 || o.precision > FFTH_MIXED) return false;
   if (!(o.tol > 0.0) || o.max_iter < 1 || o.check_every < 1) return false;
   if (o.precision == FFTH_MIXED && (!(o.inner_tol > 0.0) || o.inner_tol >= 1.0 || o.max_outer < 1)) return false;
@@ -586,6 +587,22 @@ DescSet active_set(ffth_plan* P, Role r, int state_base, int nl, int region) {
 
 // ---- solve loops ----------------------------------------------------------
 
+// One BiCGSTAB iteration (two operator applications): p and tau(p) [x-forward,
+// applying the previous iteration's x and r updates], v = A p and <r^,v>,
+// alpha; s = r - alpha v and tau(s), t = A s and the five sums, omega, beta.
+template <typename T> ffth_status bicg_iter(ffth_plan* P, const Desc* d, int nb) {
+  ffth_status s;
+  if (nb <= 0) return FFTH_OK;
+  if ((s = xfwd<T>(P, d, nb, XF_BI1)) != FFTH_OK) return s;
+  if ((s = yzy<T>(P, d, nb, OP_GAMMA)) != FFTH_OK) return s;
+  if ((s = xinv<T>(P, d, nb, XI_BI1)) != FFTH_OK) return s;
+  if ((s = fin(P, d, nb, FIN_BI_ALPHA, 0, iblocks<T>(P))) != FFTH_OK) return s;
+  if ((s = xfwd<T>(P, d, nb, XF_BI2)) != FFTH_OK) return s;
+  if ((s = yzy<T>(P, d, nb, OP_GAMMA)) != FFTH_OK) return s;
+  if ((s = xinv<T>(P, d, nb, XI_BI2)) != FFTH_OK) return s;
+  return fin(P, d, nb, FIN_BI_OMEGA, 0, iblocks<T>(P));
+}
+
 // Iterate a plain (single precision level) scheme on descriptors d with
 // states in slots [0, nl).  The iterate must hold zero on entry.
 template <typename T> ffth_status run_plain(ffth_plan* P, const Desc* d, int nl) {
@@ -594,9 +611,10 @@ template <typename T> ffth_status run_plain(ffth_plan* P, const Desc* d, int nl)
   DescSet as;
   // pass 0: x = b = -Gamma0 * P_rhs, ||b||, zero right-hand-side guard
   if ((s = apply<T>(P, d, nl, XF_LS, OP_GAMMA, XI_BS, FIN_LS_FIRST)) != FFTH_OK) return s;
-  if (o.scheme == FFTH_CG) {
+  if (o.scheme != FFTH_BASIC) {
     // r0 = b - A b = LS(x) - x
-    if ((s = apply<T>(P, d, nl, XF_LS, OP_GAMMA, XI_RESID, FIN_RESID_INIT)) != FFTH_OK) return s;
+    const int fin_op = o.scheme == FFTH_CG ? FIN_RESID_INIT : FIN_BI_INIT;
+    if ((s = apply<T>(P, d, nl, XF_LS, OP_GAMMA, XI_RESID, fin_op)) != FFTH_OK) return s;
   }
   if ((s = read_states(P)) != FFTH_OK) return s;
   int it = 0;
@@ -605,11 +623,16 @@ template <typename T> ffth_status run_plain(ffth_plan* P, const Desc* d, int nl)
     if ((as = active_set(P, R_MAIN, 0, nl, 0)).n < 0) return FFTH_ERR_DEVICE;
     for (int j = 0; j < k; ++j) {
       if (o.scheme == FFTH_BASIC) s = apply<T>(P, as.d, as.n, XF_LS, OP_GAMMA, XI_BS, FIN_BS);
-      else s = apply<T>(P, as.d, as.n, XF_CG, OP_GAMMA, XI_CG, FIN_CG_BETA);
+      else if (o.scheme == FFTH_CG) s = apply<T>(P, as.d, as.n, XF_CG, OP_GAMMA, XI_CG, FIN_CG_BETA);
+      else s = bicg_iter<T>(P, as.d, as.n);
       if (s != FFTH_OK) return s;
     }
     it += k;
     if ((s = read_states(P)) != FFTH_OK) return s;
+  }
+  if (o.scheme == FFTH_BICGSTAB) {   // the last iteration's x update of every load
+    ProfScope ps(P, C_POINT, nl);
+    HIPCHK(Launch<T>::bicg_finish(dim3(ms_blocks(P->nvox), nl), P->stream, d, 6L * P->nvox));
   }
   return FFTH_OK;
 }
@@ -788,12 +811,26 @@ void build_solve_descs(ffth_plan* P, int nl, const double* E, double* eps, bool 
       if (o.scheme == FFTH_CG) {
         m.r = f64_ptr(P, l, 0);
         m.p = f64_ptr(P, l, 1);
+      } else if (o.scheme == FFTH_BICGSTAB) {
+        m.r = f64_ptr(P, l, 0);
+        m.rh = f64_ptr(P, l, 1);
+        m.p = f64_ptr(P, l, 2);
+        m.v = f64_ptr(P, l, 3);
+        m.s = f64_ptr(P, l, 4);
+        m.t = f64_ptr(P, l, 5);
       }
     } else if (o.precision == FFTH_FP32) {
       m.x = f32_ptr(P, l, 0);
       if (o.scheme == FFTH_CG) {
         m.r = f32_ptr(P, l, 1);
         m.p = f32_ptr(P, l, 2);
+      } else if (o.scheme == FFTH_BICGSTAB) {
+        m.r = f32_ptr(P, l, 1);
+        m.rh = f32_ptr(P, l, 2);
+        m.p = f32_ptr(P, l, 3);
+        m.v = f32_ptr(P, l, 4);
+        m.s = f32_ptr(P, l, 5);
+        m.t = f32_ptr(P, l, 6);
       }
     } else {  // MIXED: outer FP64 pass
       m.x = epsl;
@@ -915,7 +952,8 @@ ffth_status solve_finish(ffth_plan* P, int nl, double* eps, ffth_result* res, do
       r.projections = m.proj;
     } else {
       r.iters = m.iters;
-      r.fp64_applications = o.precision == FFTH_FP64 ? m.iters + (o.scheme == FFTH_CG ? 2 : 1) : 0;
+      const int apps = o.scheme == FFTH_BICGSTAB ? 2 * m.iters + 2 : m.iters + (o.scheme == FFTH_CG ? 2 : 1);
+      r.fp64_applications = o.precision == FFTH_FP64 ? apps : 0;
     }
     r.residual = m.res;
     for (int c = 0; c < 6; ++c) r.mean_stress[c] = po.sums[c] / (double)P->nvox;

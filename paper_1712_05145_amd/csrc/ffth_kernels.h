@@ -135,6 +135,13 @@ __device__ __forceinline__ void apply_mat(const T* mat, int ph, bool delta, cons
 template <typename T> __device__ __forceinline__ T frob_w(const T (&a)[6], const T (&b)[6]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + T(2) * (a[3] * b[3] + a[4] * b[4] + a[5] * b[5]);
 }
+// a : b (off-diagonal tensor components counted twice) accumulated in FP64
+template <typename T> __device__ __forceinline__ double frob_d(const T (&a)[6], const T (&b)[6]) {
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 6; ++c) s += (c < 3 ? 1.0 : 2.0) * (double)a[c] * (double)b[c];
+  return s;
+}
 // C0 inner product density lam0 tr a tr b + 2 mu0 a:b
 __device__ __forceinline__ double c0_ip(double lam0, double mu0, const double (&a)[6], const double (&b)[6]) {
   const double ta = a[0] + a[1] + a[2], tb = b[0] + b[1] + b[2];
@@ -303,6 +310,53 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
         acc0 += c0_ip(d.lam0, d.mu0, rd, rd);
         acc1 += (double)frob_w(r, cr);
         acc2 += rd[0] * rd[0] + rd[1] * rd[1] + rd[2] * rd[2] + 2.0 * (rd[3] * rd[3] + rd[4] * rd[4] + rd[5] * rd[5]);
+      } else if (mode == XF_BI1) {
+        // BiCGSTAB, first pass of an iteration.  First iteration: p = r^ = r_0.
+        // Later: the previous iteration's x += alpha p + omega s and r = s - omega t,
+        // then p = r + beta (p - omega v).  tau = (C - C0) p.
+        T* rp = (T*)d.r;
+        T* pp = (T*)d.p;
+        T p[6];
+        if (first) {
+          T* rh = (T*)d.rh;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            const T rv = rp[c * nvox + vox];
+            rh[c * nvox + vox] = rv;
+            pp[c * nvox + vox] = rv;
+            p[c] = rv;
+          }
+        } else {
+          T* xp = (T*)d.x;
+          const T* sp = (const T*)d.s;
+          const T* tp = (const T*)d.t;
+          const T* vp = (const T*)d.v;
+          const T al = (T)d.st->alpha, om = (T)d.st->omega;
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            const long i = c * nvox + vox;
+            const T sv = sp[i], po = pp[i];
+            xp[i] += al * po + om * sv;
+            const T rv = sv - om * tp[i];
+            rp[i] = rv;
+            p[c] = rv + beta * (po - om * vp[i]);
+            pp[i] = p[c];
+          }
+        }
+        apply_mat<T, ISO>(mat, ph, true, p, tau);
+      } else if (mode == XF_BI2) {
+        // BiCGSTAB, second pass: s = r - alpha v, tau = (C - C0) s
+        const T* rp = (const T*)d.r;
+        const T* vp = (const T*)d.v;
+        T* sp = (T*)d.s;
+        const T al = (T)d.st->alpha;
+        T sv[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          sv[c] = rp[c * nvox + vox] - al * vp[c * nvox + vox];
+          sp[c * nvox + vox] = sv[c];
+        }
+        apply_mat<T, ISO>(mat, ph, true, sv, tau);
       } else if (mode == XF_C0) {
         // tau = C0 : r for the projection -Gamma0 * C0 r (r is the FP64 residual)
         const double* vp = (const double*)d.r;
@@ -348,7 +402,7 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
   lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, +1>(z, tw);
 
   const T alpha = (T)d.st->alpha;
-  double acc0 = 0.0, acc1 = 0.0;
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0;
   for (int v = threadIdx.x; v < ROWS * N2; v += NTB) {
     const int rr = v / N2, i2 = v % N2;
     const long row = row0 + rr;
@@ -419,6 +473,37 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
       }
       acc0 += rc[0] * rc[0] + rc[1] * rc[1] + rc[2] * rc[2] + 2.0 * (rc[3] * rc[3] + rc[4] * rc[4] + rc[5] * rc[5]);
       acc1 += c0_ip(d.lam0, d.mu0, rc, rc);
+    } else if (mode == XI_BI1) {
+      // BiCGSTAB: v = A p = p - eta; <r^, v>
+      const T* pp = (const T*)d.p;
+      const T* rh = (const T*)d.rh;
+      T* vp = (T*)d.v;
+      T v[6], h[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        v[c] = pp[c * nvox + vox] - eta[c];
+        vp[c * nvox + vox] = v[c];
+        h[c] = rh[c * nvox + vox];
+      }
+      acc0 += frob_d(h, v);
+    } else if (mode == XI_BI2) {
+      // BiCGSTAB: t = A s = s - eta; <t,s>, <t,t>, <r^,s>, <r^,t>, <s,s>
+      const T* sp = (const T*)d.s;
+      const T* rh = (const T*)d.rh;
+      T* tp = (T*)d.t;
+      T sv[6], tv[6], h[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        sv[c] = sp[c * nvox + vox];
+        tv[c] = sv[c] - eta[c];
+        tp[c * nvox + vox] = tv[c];
+        h[c] = rh[c * nvox + vox];
+      }
+      acc0 += frob_d(tv, sv);
+      acc1 += frob_d(tv, tv);
+      acc2 += frob_d(h, sv);
+      acc3 += frob_d(h, tv);
+      acc4 += frob_d(sv, sv);
     } else {  // XI_CG: q = p - eta; x += alpha p; r -= alpha q
       T* xp = (T*)d.x;
       T* rp = (T*)d.r;
@@ -437,8 +522,13 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
       acc1 += r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + 2.0 * (r[3] * r[3] + r[4] * r[4] + r[5] * r[5]);
     }
   }
-  double sums[2] = {acc0, acc1};
-  block_sums<2, NTB>(sums, d.part_i + blockIdx.x, gridDim.x);
+  if (mode == XI_BI2) {
+    double sums[5] = {acc0, acc1, acc2, acc3, acc4};
+    block_sums<5, NTB>(sums, d.part_i + blockIdx.x, gridDim.x);
+  } else {
+    double sums[2] = {acc0, acc1};
+    block_sums<2, NTB>(sums, d.part_i + blockIdx.x, gridDim.x);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -526,6 +616,20 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
   store_rows_r2c<T, N2, ROWS, NTB>(spec, z, row0, rows_total);
   double sums[3] = {acc0, acc1, acc2};
   block_sums<3, NTB>(sums, d.part_i + blockIdx.x, gridDim.x);
+}
+
+// BiCGSTAB: apply the last iteration's x += alpha p + omega s to loads that
+// stopped (the next iteration's first pass would have done it).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_bicg_finish(const Desc* __restrict__ descs, long n) {
+  const Desc& d = descs[blockIdx.y];
+  const SolverState* st = d.st;
+  if (st->active || !st->pending) return;
+  T* xp = (T*)d.x;
+  const T* pp = (const T*)d.p;
+  const T* sp = (const T*)d.s;
+  const T al = (T)st->alpha, om = (T)st->omega;
+  for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) xp[i] += al * pp[i] + om * sp[i];
 }
 
 // ---------------------------------------------------------------------------

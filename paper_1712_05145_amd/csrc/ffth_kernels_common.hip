@@ -32,6 +32,9 @@ __device__ static void fin_slots(int op, int& nf, int& ni) {
     case FIN_PROJ: ni = 2; break;
     case FIN_CG3_INIT: nf = 3; break;
     case FIN_CG3: ni = 3; break;
+    case FIN_BI_INIT: ni = 1; break;
+    case FIN_BI_ALPHA: ni = 1; break;
+    case FIN_BI_OMEGA: ni = 5; break;
     case FIN_SUMS_I: case FIN_O1RHS: ni = NRED; break;
   }
 }
@@ -147,6 +150,56 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
         st->rr = si[0];
         st->alpha = g;
         st->beta = om;
+        fin_check(st);
+      }
+      break;
+    }
+    case FIN_BI_INIT:
+      // BiCGSTAB start: r_0 = b - A b, rho = <r^, r_0> = ||r_0||^2
+      st->rr = si[0];
+      st->res = sqrt(si[0] / st->nb2);
+      st->alpha = st->omega = 1.0;
+      st->beta = 0.0;
+      st->first = 1;
+      st->pending = 0;
+      if (st->res < st->tol) {
+        st->flag = FLAG_CONVERGED;
+        st->active = 0;
+      }
+      break;
+    case FIN_BI_ALPHA: {
+      // alpha = rho / <r^, v>; the previous x update is applied by now
+      st->pending = 0;
+      const double rv = si[0];
+      if (!(fabs(rv) > 0.0) || !(rv == rv)) {
+        st->flag = FLAG_DIVERGED;
+        st->active = 0;
+      } else {
+        st->alpha = st->rr / rv;
+      }
+      break;
+    }
+    case FIN_BI_OMEGA: {
+      // si = (<t,s>, <t,t>, <r^,s>, <r^,t>, <s,s>)
+      const double ts = si[0], tt = si[1];
+      const double om = tt > 0.0 ? ts / tt : 0.0;
+      const double rho = si[2] - om * si[3];
+      const double r2 = fmax(0.0, si[4] - 2.0 * om * ts + om * om * tt);   // ||s - omega t||^2
+      st->omega = om;
+      st->pending = 1;
+      st->first = 0;
+      st->iters++;
+      st->total++;
+      st->res = sqrt(r2 / st->nb2);
+      if (st->res < st->tol) {
+        st->flag = FLAG_CONVERGED;
+        st->active = 0;
+      } else if (!(om != 0.0) || !(rho == rho) || !(fabs(rho) > 0.0)) {
+        st->flag = FLAG_DIVERGED;   // breakdown
+        st->active = 0;
+      } else {
+        st->beta = (rho / st->rr) * (st->alpha / om);
+        st->rr = rho;
         fin_check(st);
       }
       break;

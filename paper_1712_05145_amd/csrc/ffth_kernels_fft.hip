@@ -136,6 +136,11 @@ template <typename T> hipError_t Launch<T>::zpass(int n0, int v, dim3 grid, hipS
   return hipErrorInvalidValue;
 }
 
+template <typename T> hipError_t Launch<T>::bicg_finish(dim3 grid, hipStream_t s, const Desc* d, long n) {
+  hipLaunchKernelGGL((k_bicg_finish<T>), grid, dim3(NT), 0, s, d, n);
+  return hipGetLastError();
+}
+
 template struct Launch<R>;
 
 }  // namespace ffth

@@ -29,6 +29,8 @@ template <typename T> struct Launch {
                          long nvox);
   // fused three-term CG iteration (x-inverse, update, x-forward); x-inverse tiles
   static hipError_t xcg3(int n2, bool iso, int v, dim3 grid, hipStream_t s, const Desc* d, long rows, long nvox);
+  // BiCGSTAB: the pending x update of loads that stopped (n = 6 * voxels)
+  static hipError_t bicg_finish(dim3 grid, hipStream_t s, const Desc* d, long n);
   static hipError_t ypass(int n1, int v, dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols, int ntiles);
   static hipError_t zpass(int n0, int v, dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h,
                           double scale);

@@ -24,6 +24,9 @@ struct SolverState {
   int32_t max_iter;  // stop (unconverged) after this many iterations
   int32_t fp64_apps; // FP64 operator applications (outer state only)
   int32_t proj;      // FP32 projection passes (outer state only)
+  double omega;      // BiCGSTAB: omega of the last iteration
+  int32_t pending;   // BiCGSTAB: x += alpha p + omega s of the last iteration not applied yet
+  int32_t pad;
 };
 
 enum : int32_t { FLAG_RUNNING = 0, FLAG_CONVERGED = 1, FLAG_DIVERGED = 2, FLAG_ZERO_RHS = 3 };
@@ -42,6 +45,10 @@ struct Desc {
   float* delta1;           // its second slot when the inner solve is the three-term CG (or null)
   void* x1;                // three-term CG: second iterate slot (x_{k-1}, overwritten by x_{k+1})
   void* r1;                // three-term CG: second residual slot
+  void* rh;                // BiCGSTAB: shadow residual r^ = r_0
+  void* v;                 // BiCGSTAB: v = A p
+  void* s;                 // BiCGSTAB: s = r - alpha v
+  void* t;                 // BiCGSTAB: t = A s
   const double* P;         // stored right-hand-side polarization [6][N] (or null: C:E)
   void* io;                // generic input field (copy-in mode; order-1 p_2 output)
   void* out;               // generic output field (store / accumulate modes)
@@ -59,15 +66,18 @@ struct Desc {
 };
 
 // x-pass (forward) modes
-enum : int32_t { XF_LS = 0, XF_MATVEC = 1, XF_CG = 2, XF_COPY = 3, XF_C0 = 4, XF_R3 = 5 };
+enum : int32_t { XF_LS = 0, XF_MATVEC = 1, XF_CG = 2, XF_COPY = 3, XF_C0 = 4, XF_R3 = 5, XF_BI1 = 6, XF_BI2 = 7 };
 // x-pass (inverse) modes
-enum : int32_t { XI_STORE = 0, XI_ACCUM = 1, XI_BS = 2, XI_RESID = 3, XI_BS_INNER = 4, XI_CG = 5, XI_PROJ = 6 };
+enum : int32_t {
+  XI_STORE = 0, XI_ACCUM = 1, XI_BS = 2, XI_RESID = 3, XI_BS_INNER = 4, XI_CG = 5, XI_PROJ = 6, XI_BI1 = 7, XI_BI2 = 8
+};
 // spectral operators of the z-pass
 enum : int32_t { OP_GAMMA = 0, OP_THETA = 1, OP_DISP = 2 };
 // finalize operations
 enum : int32_t {
   FIN_LS_FIRST = 0, FIN_BS = 1, FIN_RESID_INIT = 2, FIN_CG_ALPHA = 3, FIN_CG_BETA = 4,
-  FIN_OUTER = 5, FIN_SUMS_I = 6, FIN_O1RHS = 7, FIN_OUTER_P = 8, FIN_PROJ = 9, FIN_CG3_INIT = 10, FIN_CG3 = 11
+  FIN_OUTER = 5, FIN_SUMS_I = 6, FIN_O1RHS = 7, FIN_OUTER_P = 8, FIN_PROJ = 9, FIN_CG3_INIT = 10, FIN_CG3 = 11,
+  FIN_BI_INIT = 12, FIN_BI_ALPHA = 13, FIN_BI_OMEGA = 14
 };
 
 constexpr int NRED = 8;   // doubles per block in the partial-sum arrays

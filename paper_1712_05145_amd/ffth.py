@@ -19,10 +19,10 @@ LIBPATH = os.path.join(HERE, "libffth.so")
 
 FFTH_OK, FFTH_ERR_INVALID, FFTH_ERR_OOM, FFTH_ERR_NOT_CONVERGED, FFTH_ERR_DIVERGED, \
     FFTH_ERR_DEVICE, FFTH_ERR_BUSY, FFTH_ERR_CANCELLED = range(8)
-FFTH_BASIC, FFTH_CG = 0, 1
+FFTH_BASIC, FFTH_CG, FFTH_BICGSTAB = 0, 1, 2
 FFTH_FP64, FFTH_FP32, FFTH_MIXED = 0, 1, 2
 
-SCHEMES = {"basic": FFTH_BASIC, "cg": FFTH_CG}
+SCHEMES = {"basic": FFTH_BASIC, "cg": FFTH_CG, "bicgstab": FFTH_BICGSTAB}
 PRECISIONS = {"fp64": FFTH_FP64, "fp32": FFTH_FP32, "mixed": FFTH_MIXED}
 
 

@@ -46,6 +46,12 @@ def test_supported_sizes_and_workspace():
     assert ffth.ffth_workspace_bytes((32, 32, 32), 2, 1, 1, o) > b1
     bad = ffth.make_opts(tol=-1.0)
     assert ffth.ffth_workspace_bytes((16, 16, 16), 2, 1, 0, bad) == 0
+    # BiCGSTAB keeps six FP64 (or seven FP32) fields; it has no mixed-precision form
+    cg64 = ffth.ffth_workspace_bytes((32, 32, 32), 2, 1, 0, ffth.make_opts("cg", "fp64"))
+    bi64 = ffth.ffth_workspace_bytes((32, 32, 32), 2, 1, 0, ffth.make_opts("bicgstab", "fp64"))
+    assert bi64 >= cg64 + 4 * 32 ** 3 * 6 * 8
+    assert ffth.ffth_workspace_bytes((32, 32, 32), 2, 1, 0, ffth.make_opts("bicgstab", "fp32")) > 0
+    assert ffth.ffth_workspace_bytes((32, 32, 32), 2, 1, 0, ffth.make_opts("bicgstab", "mixed")) == 0
 
 
 def _problem(n=(16, 16, 16), lam0=1.0, mu0=1.0):

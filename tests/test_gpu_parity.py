@@ -154,7 +154,9 @@ def test_zero_rhs_reference_equals_material():
     torch = require_gpu()
     phase = np.zeros((8, 8, 8), dtype=np.uint16)
     for prec in ("fp64", "fp32", "mixed"):
-        for scheme in ("basic", "cg"):
+        for scheme in ("basic", "cg", "bicgstab"):
+            if prec == "mixed" and scheme == "bicgstab":
+                continue
             s = ffth.Solver(phase, 1.3, 0.8, lame=[[1.3, 0.8]], scheme=scheme, precision=prec)
             eps, res = s.solve_order0([1.0, 0.5, 0, 0.2, 0, 0])
             assert res[0]["status"] == 0 and res[0]["iters"] == 0
@@ -377,3 +379,76 @@ def test_mixed_three_term_inner_iterations_track_fp64_cg():
         its[precision] = sum(r["iters"] for r in res)
     print("iterations", its)
     assert its["mixed"] <= 1.3 * its["fp64"] + 12
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_bicgstab_order0_parity_sphere16(sphere16_oracle, precision):
+    """BiCGSTAB (the paper's solver) on the six unit loads in one batched call."""
+    torch = require_gpu()
+    print("case bicgstab order0", precision, flush=True)
+    phase, lame, lam0, mu0, ceff, corr, _ = sphere16_oracle
+    tol, ftol = (1e-10, 1e-6) if precision == "fp64" else (1e-5, 1e-4)
+    s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, scheme="bicgstab", precision=precision, tol=tol)
+    eps, res = s.solve_order0(np.eye(6))
+    eps = eps.cpu().numpy()
+    for J in range(6):
+        assert res[J]["status"] == 0, res[J]
+        assert rel_l2(eps[J], voigt6(corr[J])) < ftol, (J, rel_l2(eps[J], voigt6(corr[J])))
+    if precision == "fp64":
+        _, ok = _ceff_close(np.array([r["mean_stress"] for r in res]).T, ceff)
+        assert ok
+
+
+def test_bicgstab_iterations_and_residual_match_oracle():
+    """Same iterates as the oracle's BiCGSTAB: iteration count and final residual."""
+    torch = require_gpu()
+    phase, lame, lam0, mu0 = _sphere(16, contrast=50.0)
+    prob = H.make_problem(phase, lam0, mu0, lame=lame)
+    E = [1.0, 0.0, 0.0, 0.0, 0.0, 0.0]
+    _, mean_ref, info = H.solve_order0(prob, E, "bicgstab", tol=1e-8)
+    s = ffth.Solver(phase, lam0, mu0, lame=lame, scheme="bicgstab", precision="fp64", tol=1e-8, check_every=1)
+    _, res = s.solve_order0(E)
+    print("bicgstab iterations gpu", res[0]["iters"], "oracle", info["iters"])
+    assert abs(res[0]["iters"] - info["iters"]) <= 1
+    assert res[0]["residual"] < 1e-8
+    assert res[0]["fp64_applications"] == 2 * res[0]["iters"] + 2
+
+
+def test_bicgstab_generic_stiffness_and_order1():
+    """Generic (anisotropic) phases on a non-cubic ragged grid, and the order-1
+    problem, with BiCGSTAB in FP64."""
+    torch = require_gpu()
+    shape, seed = (12, 16, 8), 3
+    rng = np.random.default_rng(seed)
+    phase = M.random_phases(shape, 3, seed)
+    v21 = []
+    for _ in range(3):
+        a = rng.standard_normal((6, 6))
+        c = a @ a.T + 6 * np.eye(6)
+        v21.append([c[i, j] for i in range(6) for j in range(i, 6)])
+    v21 = np.array(v21)
+    prob = H.make_problem(phase, 3.0, 3.0, voigt21=v21)
+    E = np.array([0.3, -1.0, 0.5, 0.2, 0.0, 1.0])
+    eps_ref, mean_ref, _ = H.solve_order0(prob, E, "cg", tol=1e-12)
+    s = ffth.Solver(phase, 3.0, 3.0, voigt21=v21, scheme="bicgstab", precision="fp64", tol=1e-10)
+    eps, res = s.solve_order0(E)
+    assert rel_l2(eps[0].cpu().numpy(), voigt6(eps_ref)) < 1e-6
+    assert np.allclose(res[0]["mean_stress"], mean_ref, rtol=1e-7, atol=1e-9 * np.abs(mean_ref).max())
+    # order 1 from the oracle's correctors
+    phase, lame, lam0, mu0 = _sphere(12)
+    prob = H.make_problem(phase, lam0, mu0, lame=lame)
+    _, corr, _ = H.effective_stiffness(prob, "cg", tol=1e-12)
+    grad = np.random.default_rng(8).standard_normal((6, 3))
+    eps2_ref, _ = H.solve_order1(prob, corr, grad, "cg", tol=1e-12)
+    eps0 = to_dev(torch, np.stack([voigt6(c) for c in corr]))
+    s1 = ffth.Solver(phase, lam0, mu0, lame=lame, order=1, nloads=1, scheme="bicgstab", precision="fp64", tol=1e-10)
+    eps2, res = s1.solve_order1(eps0, grad.reshape(1, 18))
+    assert res[0]["status"] == 0
+    assert rel_l2(eps2[0].cpu().numpy(), voigt6(eps2_ref)) < 1e-6
+
+
+def test_bicgstab_mixed_rejected():
+    torch = require_gpu()
+    with pytest.raises(ffth.FFTHError):
+        ffth.Solver(np.zeros((8, 8, 8), np.uint16), 1.0, 1.0, lame=[[1.0, 1.0]], scheme="bicgstab",
+                    precision="mixed")

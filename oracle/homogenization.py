@@ -119,6 +119,72 @@ def solve_order1(prob, correctors, grad, scheme="cg", tol=1e-12, max_iter=100000
     return eps, info
 
 
+def order1_unit_solutions(prob, correctors, scheme="cg", tol=1e-12, max_iter=100000):
+    """The 18 order-1 solutions for unit gradient loads G[J, j] = 1 (index
+    J * 3 + j): strains eps_2^(J,j) (3,3,...) and their mean stresses."""
+    sols, means = [], []
+    for J in range(6):
+        for j in range(3):
+            grad = np.zeros((6, 3))
+            grad[J, j] = 1.0
+            eps, info = solve_order1(prob, correctors, grad, scheme, tol, max_iter)
+            sols.append(eps)
+            means.append(info["mean_stress"])
+    return sols, np.array(means)
+
+
+def order2_rhs(prob, correctors, order1_solutions, hess):
+    """Right-hand side of the problem of the paper's order alpha = 3 (Sec. 3,
+    the definition of p_alpha and g_alpha for alpha >= 3).
+
+    correctors: six order-0 strain fields; order1_solutions: the 18 order-1
+    strain fields for unit gradient loads G[J, j] = 1 (index J * 3 + j);
+    hess: (6, 3, 3) array H[J, j, m] = d^2 E_kl / dY_j dY_m (symmetric in j, m).
+    With u_2 = sum_{J,j} G[J, j] w^(J,j) (w the displacement of the unit
+    solution J, j) and G[J, j](Y) = dE_J/dY_j, so that dG[J, j]/dY_m = H[J, j, m]:
+
+      (X_2 . H)_am = sum_{J,j} w^(J,j)_a H[J, j, m]
+      p_3 = C : sym(X_2 . H)                                (p_alpha, alpha = 3)
+      S_2^(J,j) = C : eps_2^(J,j) + p_2^(J,j),   p_2^(J,j) = C : sym(c_J X_1[:, J] x e_j)
+      g_i = sum_{J,j,m} S_2^(J,j)_im H[J, j, m]   (= div_Y [C : (e_y(u_2) + e_Y(u_1))])
+      theta_3 from g by eq. (12) with the mean of g dropped.
+    Returns (P = p_3 + theta_3, p_3, theta_3, g, <g>).
+    """
+    hess = np.asarray(hess, dtype=np.float64).reshape(6, 3, 3)
+    shape = prob.shape
+    v = np.zeros((3, 3) + shape)
+    g = np.zeros((3,) + shape)
+    x1 = [spectral.displacement_from_strain(correctors[J]) for J in range(6)]
+    eye = np.eye(3)
+    for J in range(6):
+        for j in range(3):
+            h = hess[J, j]                                           # (3,) over m
+            if not np.any(h):
+                continue
+            e2 = order1_solutions[J * 3 + j]
+            w = spectral.displacement_from_strain(e2)
+            v += np.einsum("a...,m->am...", w, h)
+            xe = MULT[J] * np.einsum("a...,j->aj...", x1[J], eye[j])   # c_J X_1[:, J] x e_j
+            p2 = prob.C.contract(0.5 * (xe + np.swapaxes(xe, 0, 1)))
+            s2 = prob.C.contract(e2) + p2
+            g += np.einsum("im...,m->i...", s2, h)
+    p3 = prob.C.contract(0.5 * (v + np.swapaxes(v, 0, 1)))
+    theta = spectral.theta_from_g(g)
+    return p3 + theta, p3, theta, g, g.mean(axis=(1, 2, 3))
+
+
+def solve_order2(prob, correctors, order1_solutions, hess, scheme="cg", tol=1e-12, max_iter=100000):
+    """Problem of the paper's order 3: returns (eps_3, info) with info['g_mean']
+    and info['mean_stress'] = Voigt of <C : eps_3 + p_3>."""
+    p_rhs, p3, theta, g, g_mean = order2_rhs(prob, correctors, order1_solutions, hess)
+    scale = (tensors.l2norm(p3) + tensors.l2norm(g)) / (2.0 * abs(prob.mu0))
+    eps, info = _solve(prob, p_rhs, scheme, tol, max_iter, scale)
+    info["g_mean"] = g_mean
+    info["mean_stress"] = tensors.stress_voigt_from_tensor(
+        (prob.C.contract(eps) + p3).mean(axis=(2, 3, 4)))
+    return eps, info
+
+
 # ---------------------------------------------------------------------------
 # Bounds on the effective stiffness
 # ---------------------------------------------------------------------------

@@ -133,7 +133,7 @@ int32_t ffth_size_supported(int32_t n);
 
 /* Bytes of caller-owned device workspace needed by a plan for grids of size
  * n[3], a phase table of `nphases` entries, up to `nloads` simultaneous load
- * cases, order 0 or 1 and the given options.  Returns 0 for invalid
+ * cases, order 0, 1 or 2 and the given options.  Returns 0 for invalid
  * arguments. */
 size_t ffth_workspace_bytes(const int32_t n[3], int32_t nphases, int32_t nloads, int32_t order,
                             const ffth_opts *o);
@@ -167,6 +167,30 @@ ffth_status ffth_solve_order0(ffth_plan *plan, int32_t nloads, const double *E, 
  *   eps:      DEVICE FP64 out [nloads][6][N]. */
 ffth_status ffth_solve_order1(ffth_plan *plan, const double *eps0_six, int32_t nloads,
                               const double *G, double *eps, ffth_result *res);
+
+/* Order 2, the problem of the paper's order alpha = 3 (Sec. 3, the definition
+ * of p_alpha and g_alpha for alpha >= 3), read as the next step of the same
+ * recursion: with u_2 = sum G[J,j] w^(J,j) the order-1 displacement and
+ * H[J,j,m] = dG[J,j]/dY_m,
+ *   p_3 = C : sym(X_2 . H),      (X_2 . H)_am = sum_{J,j} w^(J,j)_a H[J,j,m]
+ *   g_3 = div_Y[C : (e_y(u_2) + e_Y(u_1))],  g_i = sum_{J,j,m} S^(J,j)_im H[J,j,m]
+ * with S^(J,j) = C : eps1^(J,j) + p_2^(J,j) the local order-1 stress of the
+ * unit gradient load; theta_3 from g by eq. (12), then the same iteration.
+ * The plan must have been created with order 2.
+ *   eps0_six: DEVICE FP64 [6][6][N] as for order 1.
+ *   eps1_18:  DEVICE FP64 [18][6][N] order-1 solutions (ffth_solve_order1) for
+ *             the unit gradient loads G[J*3 + j] = 1, in the order J*3 + j.
+ *   H:        HOST [nloads][54], H[J*9 + j*3 + m] = d^2 E_J / dY_j dY_m
+ *             (tensor components J, symmetric in j, m).
+ *   eps:      DEVICE FP64 out [nloads][6][N]; res: mean_stress = <C:eps + p_3>,
+ *             g_mean = <g_3>. */
+ffth_status ffth_solve_order2(ffth_plan *plan, const double *eps0_six, const double *eps1_18,
+                              int32_t nloads, const double *H, double *eps, ffth_result *res);
+
+/* Order-2 right-hand side polarization P = p_3 + theta_3 for one load H [54]
+ * (arguments as for ffth_solve_order2); P: DEVICE FP64 out [6][N]. */
+ffth_status ffth_order2_rhs(ffth_plan *plan, const double *eps0_six, const double *eps1_18,
+                            const double *H, double *P, double *g_mean);
 
 /* Green operator application eta = -Gamma0 * tau (eq. (5) and the formula
  * below it; the Fourier-space steps of Algorithm 1), one 6-component field.

@@ -51,7 +51,7 @@ bool hip_ok(hipError_t e, const char* what) {
 // Workspace regions (byte offsets).  Computed identically for sizing and
 // for carving a caller's buffer.
 struct Layout {
-  size_t mat64, mat32, desc, cdesc, state, part, spec, f32, f64, P, X1, g, misc, total;
+  size_t mat64, mat32, desc, cdesc, state, part, spec, f32, f64, P, X1, X2, g, misc, total;
   size_t spec_stride, f32_stride, f64_stride, part_stride;
   int nf32, nf64;
   int ndesc, nstate, nblk;
@@ -94,11 +94,13 @@ Layout make_layout(const int n[3], int nph, int nloads, int order, const ffth_op
   L.f32 = off; off += (size_t)nloads * L.nf32 * L.f32_stride;
   L.f64 = off; off += (size_t)nloads * L.nf64 * L.f64_stride;
   L.P = off;
-  if (order == 1) off += (size_t)nloads * L.f64_stride;
-  L.X1 = off;
-  if (order == 1) off += al((size_t)nvox * 18 * sizeof(double));
+  if (order >= 1) off += (size_t)nloads * L.f64_stride;
+  L.X1 = off;                                   // order-0 corrector displacements [6][3][N]
+  if (order >= 1) off += al((size_t)nvox * 18 * sizeof(double));
+  L.X2 = off;                                   // order-1 unit-gradient displacements [18][3][N]
+  if (order == 2) off += al((size_t)nvox * 54 * sizeof(double));
   L.g = off;
-  if (order == 1) off += (size_t)nloads * al((size_t)nvox * 3 * sizeof(double));
+  if (order >= 1) off += (size_t)nloads * al((size_t)nvox * 3 * sizeof(double));
   L.total = off;
   return L;
 }
@@ -188,6 +190,7 @@ double* f64_ptr(ffth_plan* P, int l, int k) {
 }
 double* Pfield(ffth_plan* P, int l) { return (double*)(P->ws + P->L.P + (size_t)l * P->L.f64_stride); }
 double* X1field(ffth_plan* P) { return (double*)(P->ws + P->L.X1); }
+double* X2field(ffth_plan* P) { return (double*)(P->ws + P->L.X2); }
 double* gfield(ffth_plan* P, int l) {
   return (double*)(P->ws + P->L.g + (size_t)l * al((size_t)P->nvox * 3 * sizeof(double)));
 }
@@ -999,7 +1002,7 @@ void ffth_default_opts(ffth_opts* o) {
 int32_t ffth_size_supported(int32_t n) { return size_supported(n) ? 1 : 0; }
 
 size_t ffth_workspace_bytes(const int32_t n[3], int32_t nphases, int32_t nloads, int32_t order, const ffth_opts* o) {
-  if (!n || !o || nloads < 1 || nphases < 1 || nphases > 65535 || (order != 0 && order != 1)) return 0;
+  if (!n || !o || nloads < 1 || nphases < 1 || nphases > 65535 || order < 0 || order > 2) return 0;
   int nn[3] = {n[0], n[1], n[2]};
   if (!grid_supported(nn) || !opts_valid(*o)) return 0;
   return make_layout(nn, nphases, nloads, order, *o).total;
@@ -1054,7 +1057,7 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
     g_last_error = "CG needs a positive definite reference medium";
     return FFTH_ERR_INVALID;
   }
-  if (!opts_valid(*o) || nloads < 1 || (order != 0 && order != 1)) {
+  if (!opts_valid(*o) || nloads < 1 || order < 0 || order > 2) {
     g_last_error = "bad options";
     return FFTH_ERR_INVALID;
   }
@@ -1181,13 +1184,18 @@ ffth_status ffth_solve_order0(ffth_plan* P, int32_t nloads, const double* E, dou
 namespace {
 
 // Order-1 polarization P_l = p_2 + theta_2 for nl gradient loads (X1 built).
-ffth_status build_order1_rhs(ffth_plan* P, int nl, const double* eps0, const double* G, double* const* Pout,
-                             std::vector<double>& gmean) {
+// Right-hand side P = p + theta of order 1 (G: [nl][18], pointwise data eps0,
+// X1) or order 2 (G: [nl][54] second gradients, pointwise data eps1, X1, X2).
+ffth_status build_rhs(ffth_plan* P, int order, int nl, const double* eps, const double* G, double* const* Pout,
+                      std::vector<double>& gmean) {
   ffth_status s;
   for (int l = 0; l < nl; ++l) {
     Desc d = base_desc(P, l);
     d.st = st_post(P, l);
-    for (int i = 0; i < 18; ++i) d.G[i] = G[18 * l + i];
+    if (order == 1)
+      for (int i = 0; i < 18; ++i) d.G[i] = G[18 * l + i];
+    else
+      for (int i = 0; i < 54; ++i) d.H[i] = G[54 * l + i];
     d.io = Pout[l];          // p_2 out (then theta accumulated)
     d.p = gfield(P, l);      // g out
     P->h_desc[desc_slot(P, R_POST, l)] = d;
@@ -1204,7 +1212,11 @@ ffth_status build_order1_rhs(ffth_plan* P, int nl, const double* eps0, const dou
   const int nms = ms_blocks(P->nvox);
   {
     ProfScope ps(P, C_POINT, nl);
-    HIPCHK(launch_order1_point(P->iso, nms, nl, P->stream, dptr(P, R_POST), eps0, X1field(P), P->nvox));
+    if (order == 1)
+      HIPCHK(launch_order1_point(P->iso, nms, nl, P->stream, dptr(P, R_POST), eps, X1field(P), P->nvox));
+    else
+      HIPCHK(launch_order2_point(P->iso, nms, nl, P->stream, dptr(P, R_POST), eps, X1field(P), X2field(P),
+                                 P->nvox));
   }
   if ((s = fin(P, dptr(P, R_POST), nl, FIN_O1RHS, 0, nms)) != FFTH_OK) return s;
   const Desc* dt = dptr(P, R_THETA);
@@ -1221,24 +1233,40 @@ ffth_status build_order1_rhs(ffth_plan* P, int nl, const double* eps0, const dou
   return FFTH_OK;
 }
 
-ffth_status make_x1(ffth_plan* P, const double* eps0) {
-  // Forward + spectral operator, then inverse, one corrector at a time so
+ffth_status make_x1_block(ffth_plan* P, const double* eps0, double* out, int count);
+
+// Displacements of `count` strain fields [count][6][N] into out [count][3][N]
+// (order-0 correctors -> X1, order-1 unit-gradient solutions -> X2).
+ffth_status make_disp(ffth_plan* P, const double* eps0, double* out, int count) {
+  ffth_status s;
+  for (int base = 0; base < count; base += 6) {
+    const int k = std::min(6, count - base);
+    if ((s = make_x1_block(P, eps0 + (size_t)base * 6 * P->nvox, out + (size_t)base * 3 * P->nvox, k)) != FFTH_OK)
+      return s;
+  }
+  return FFTH_OK;
+}
+
+ffth_status make_x1(ffth_plan* P, const double* eps0) { return make_disp(P, eps0, X1field(P), 6); }
+
+ffth_status make_x1_block(ffth_plan* P, const double* eps0, double* out, int count) {
+  // Forward + spectral operator, then inverse, one field at a time so
   // that a single spectrum buffer suffices.
   ffth_status s;
-  for (int J = 0; J < 6; ++J) {
+  for (int J = 0; J < count; ++J) {
     Desc d = base_desc(P, 0);
     d.part_f = part_ptr(P, 2 * P->nloads);
     d.part_i = part_ptr(P, 2 * P->nloads + 1);
     d.st = P->d_state + 3 * P->nloads;
     d.io = (void*)(eps0 + (size_t)J * 6 * P->nvox);
-    d.out = X1field(P) + (size_t)J * 3 * P->nvox;
+    d.out = out + (size_t)J * 3 * P->nvox;
     d.nc = 6;
     P->h_desc[util6_slot(P, J)] = d;
   }
   if ((s = upload_descs(P)) != FFTH_OK) return s;
   std::vector<SolverState> u(1, make_state(0, 1, 0, 1));
   if ((s = upload_states(P, u, 3 * P->nloads)) != FFTH_OK) return s;
-  for (int J = 0; J < 6; ++J) {
+  for (int J = 0; J < count; ++J) {
     const Desc* d = P->d_desc + util6_slot(P, J);
     if ((s = xfwd<double>(P, d, 1, XF_COPY)) != FFTH_OK) return s;
     if ((s = yzy<double>(P, d, 1, OP_DISP)) != FFTH_OK) return s;
@@ -1273,10 +1301,59 @@ ffth_status ffth_solve_order1(ffth_plan* P, const double* eps0_six, int32_t nloa
   std::vector<double*> pout(nloads);
   for (int l = 0; l < nloads; ++l) pout[l] = Pfield(P, l);
   std::vector<double> gmean;
-  if ((s = build_order1_rhs(P, nloads, eps0_six, G, pout.data(), gmean)) != FFTH_OK) return s;
+  if ((s = build_rhs(P, 1, nloads, eps0_six, G, pout.data(), gmean)) != FFTH_OK) return s;
   build_solve_descs(P, nloads, nullptr, eps, true);
   if ((s = upload_descs(P)) != FFTH_OK) return s;
   return solve_common(P, nloads, eps, res, t0, gmean.data());
+}
+
+ffth_status ffth_solve_order2(ffth_plan* P, const double* eps0_six, const double* eps1_18, int32_t nloads,
+                              const double* H, double* eps, ffth_result* res) {
+  g_last_error.clear();
+  ffth_status s = check_plan(P, nloads);
+  if (s != FFTH_OK) return s;
+  if (P->order != 2) {
+    g_last_error = "plan was not created for order 2";
+    return FFTH_ERR_INVALID;
+  }
+  if (!eps0_six || !eps1_18 || !H || !eps || !res) {
+    g_last_error = "null argument";
+    return FFTH_ERR_INVALID;
+  }
+  const double t0 = now_s();
+  if ((s = make_x1(P, eps0_six)) != FFTH_OK) return s;
+  if ((s = make_disp(P, eps1_18, X2field(P), 18)) != FFTH_OK) return s;
+  std::vector<double*> pout(nloads);
+  for (int l = 0; l < nloads; ++l) pout[l] = Pfield(P, l);
+  std::vector<double> gmean;
+  if ((s = build_rhs(P, 2, nloads, eps1_18, H, pout.data(), gmean)) != FFTH_OK) return s;
+  build_solve_descs(P, nloads, nullptr, eps, true);
+  if ((s = upload_descs(P)) != FFTH_OK) return s;
+  return solve_common(P, nloads, eps, res, t0, gmean.data());
+}
+
+ffth_status ffth_order2_rhs(ffth_plan* P, const double* eps0_six, const double* eps1_18, const double* H,
+                            double* Pout, double* g_mean) {
+  g_last_error.clear();
+  ffth_status s = check_plan(P, 1);
+  if (s != FFTH_OK) return s;
+  if (P->order != 2) {
+    g_last_error = "plan was not created for order 2";
+    return FFTH_ERR_INVALID;
+  }
+  if (!eps0_six || !eps1_18 || !H || !Pout) {
+    g_last_error = "null argument";
+    return FFTH_ERR_INVALID;
+  }
+  if ((s = make_x1(P, eps0_six)) != FFTH_OK) return s;
+  if ((s = make_disp(P, eps1_18, X2field(P), 18)) != FFTH_OK) return s;
+  std::vector<double> gm;
+  double* po[1] = {Pout};
+  if ((s = build_rhs(P, 2, 1, eps1_18, H, po, gm)) != FFTH_OK) return s;
+  if (g_mean)
+    for (int c = 0; c < 3; ++c) g_mean[c] = gm[c];
+  HIPCHK(hipStreamSynchronize(P->stream));
+  return FFTH_OK;
 }
 
 ffth_status ffth_green_apply(ffth_plan* P, const double* tau, double* eta, int32_t precision) {
@@ -1352,7 +1429,7 @@ ffth_status ffth_order1_rhs(ffth_plan* P, const double* eps0_six, const double* 
   if ((s = make_x1(P, eps0_six)) != FFTH_OK) return s;
   std::vector<double> gm;
   double* po[1] = {Pout};
-  if ((s = build_order1_rhs(P, 1, eps0_six, G, po, gm)) != FFTH_OK) return s;
+  if ((s = build_rhs(P, 1, 1, eps0_six, G, po, gm)) != FFTH_OK) return s;
   if (g_mean)
     for (int c = 0; c < 3; ++c) g_mean[c] = gm[c];
   HIPCHK(hipStreamSynchronize(P->stream));

@@ -340,6 +340,68 @@ __global__ __launch_bounds__(NT) void k_order1_point(const Desc* __restrict__ de
   block_sums<NRED, NT>(acc, d.part_i + blockIdx.x, gridDim.x);
 }
 
+// Order 2 (the paper's alpha = 3): per voxel, from the order-0 corrector
+// displacements x1 [6][3][N], the 18 order-1 unit-gradient strains eps1
+// [18][6][N] and their displacements x2 [18][3][N]:
+//   V_am = sum_{J,j} x2[J,j]_a H[J,j,m],  p_3 = C : sym(V)
+//   S_2^(J,j) = C : (eps1[J,j] + sym(c_J x1[J] x e_j)),  g_i = sum_{J,j,m} S_2^(J,j)_im H[J,j,m]
+template <bool ISO>
+__global__ __launch_bounds__(NT) void k_order2_point(const Desc* __restrict__ descs, const double* __restrict__ eps1,
+                                                     const double* __restrict__ x1, const double* __restrict__ x2,
+                                                     long nvox) {
+  const Desc& d = descs[blockIdx.y];
+  if (!d.st->active) return;
+  double acc[NRED] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double* pout = (double*)d.io;   // [6][N] p_3
+  double* gout = (double*)d.p;    // [3][N] g
+  const double mult[6] = {1, 1, 1, 2, 2, 2};
+  for (long vox = (long)blockIdx.x * NT + threadIdx.x; vox < nvox; vox += (long)gridDim.x * NT) {
+    const int ph = d.phase[vox];
+    double V[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    double g[3] = {0, 0, 0};
+    for (int jj = 0; jj < 18; ++jj) {
+      const int J = jj / 3, j = jj % 3;
+      const double h0 = d.H[jj * 3 + 0], h1 = d.H[jj * 3 + 1], h2 = d.H[jj * 3 + 2];
+      if (h0 == 0.0 && h1 == 0.0 && h2 == 0.0) continue;   // the same for every thread of the load
+      double xe[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const double w = x2[((long)jj * 3 + a) * nvox + vox];
+        V[a][0] += w * h0;
+        V[a][1] += w * h1;
+        V[a][2] += w * h2;
+        xe[a] = mult[J] * x1[((long)J * 3 + a) * nvox + vox];
+      }
+      // eps1 + sym(xe x e_j) in tensor components (11,22,33,23,13,12)
+      double e[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) e[c] = eps1[((long)jj * 6 + c) * nvox + vox];
+      if (j == 0) { e[0] += xe[0]; e[5] += 0.5 * xe[1]; e[4] += 0.5 * xe[2]; }
+      else if (j == 1) { e[1] += xe[1]; e[5] += 0.5 * xe[0]; e[3] += 0.5 * xe[2]; }
+      else { e[2] += xe[2]; e[4] += 0.5 * xe[0]; e[3] += 0.5 * xe[1]; }
+      double s[6];
+      apply_mat<double, ISO>(d.mat64, ph, false, e, s);
+      const double S[3][3] = {{s[0], s[5], s[4]}, {s[5], s[1], s[3]}, {s[4], s[3], s[2]}};
+#pragma unroll
+      for (int i = 0; i < 3; ++i) g[i] += S[i][0] * h0 + S[i][1] * h1 + S[i][2] * h2;
+    }
+    double sy[6] = {V[0][0], V[1][1], V[2][2], 0.5 * (V[1][2] + V[2][1]), 0.5 * (V[0][2] + V[2][0]),
+                    0.5 * (V[0][1] + V[1][0])};
+    double p3[6];
+    apply_mat<double, ISO>(d.mat64, ph, false, sy, p3);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) pout[c * nvox + vox] = p3[c];
+#pragma unroll
+    for (int i = 0; i < 3; ++i) gout[i * nvox + vox] = g[i];
+    acc[0] += frob_w(p3, p3);
+    acc[1] += g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    acc[2] += g[0];
+    acc[3] += g[1];
+    acc[4] += g[2];
+  }
+  block_sums<NRED, NT>(acc, d.part_i + blockIdx.x, gridDim.x);
+}
+
 __global__ void k_widen(const Desc* __restrict__ descs, long n) {
   const Desc& d = descs[blockIdx.y];
   const float* src = (const float*)d.x;
@@ -361,6 +423,8 @@ template __global__ void k_mean_stress<true>(const Desc*, long);
 template __global__ void k_mean_stress<false>(const Desc*, long);
 template __global__ void k_order1_point<true>(const Desc*, const double*, const double*, long);
 template __global__ void k_order1_point<false>(const Desc*, const double*, const double*, long);
+template __global__ void k_order2_point<true>(const Desc*, const double*, const double*, const double*, long);
+template __global__ void k_order2_point<false>(const Desc*, const double*, const double*, const double*, long);
 
 }  // namespace ffth
 
@@ -392,6 +456,13 @@ hipError_t launch_order1_point(bool iso, int nblk, int nbatch, hipStream_t s, co
                                const double* x1, long nvox) {
   if (iso) hipLaunchKernelGGL(k_order1_point<true>, dim3(nblk, nbatch), dim3(NT), 0, s, d, eps0, x1, nvox);
   else hipLaunchKernelGGL(k_order1_point<false>, dim3(nblk, nbatch), dim3(NT), 0, s, d, eps0, x1, nvox);
+  return hipGetLastError();
+}
+
+hipError_t launch_order2_point(bool iso, int nblk, int nbatch, hipStream_t s, const Desc* d, const double* eps1,
+                               const double* x1, const double* x2, long nvox) {
+  if (iso) hipLaunchKernelGGL(k_order2_point<true>, dim3(nblk, nbatch), dim3(NT), 0, s, d, eps1, x1, x2, nvox);
+  else hipLaunchKernelGGL(k_order2_point<false>, dim3(nblk, nbatch), dim3(NT), 0, s, d, eps1, x1, x2, nvox);
   return hipGetLastError();
 }
 

@@ -42,6 +42,8 @@ hipError_t launch_finalize(int nbatch, hipStream_t s, const Desc* d, int op, int
 hipError_t launch_mean_stress(bool iso, int nblk, int nbatch, hipStream_t s, const Desc* d, long nvox);
 hipError_t launch_order1_point(bool iso, int nblk, int nbatch, hipStream_t s, const Desc* d, const double* eps0,
                                const double* x1, long nvox);
+hipError_t launch_order2_point(bool iso, int nblk, int nbatch, hipStream_t s, const Desc* d, const double* eps1,
+                               const double* x1, const double* x2, long nvox);
 hipError_t launch_widen(int nbatch, hipStream_t s, const Desc* d, long n);
 hipError_t launch_phase_max(hipStream_t s, const uint16_t* phase, long n, int* out);
 

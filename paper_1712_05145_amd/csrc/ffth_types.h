@@ -60,6 +60,7 @@ struct Desc {
   double lam0, mu0;        // reference medium of this entry's problem
   double E[6];             // macroscopic strain, tensor components
   double G[18];            // order-1 gradient load G[J*3 + j]
+  double H[54];            // order-2 load H[J*9 + j*3 + m] = d^2 E_J / dY_j dY_m
   int32_t nc;              // components of io (3 or 6)
   int32_t r_f32;           // residual stored as FP32
   int32_t pad[2];

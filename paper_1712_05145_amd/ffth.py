@@ -81,6 +81,12 @@ SIGNATURES = [
     ("ffth_order1_rhs", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
       ctypes.POINTER(ctypes.c_double)]),
+    ("ffth_solve_order2", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+      ctypes.c_void_p, ctypes.POINTER(ffth_result)]),
+    ("ffth_order2_rhs", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+      ctypes.POINTER(ctypes.c_double)]),
     ("ffth_profile_enable", ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     ("ffth_profile_read", ctypes.c_int,
      [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
@@ -210,6 +216,20 @@ def ffth_order1_rhs(plan, eps0_ptr, G, p_ptr):
     return list(gm)
 
 
+def ffth_solve_order2(plan, eps0_ptr, eps1_ptr, H, eps_ptr, nloads):
+    h, hp = _darr(H)
+    res = (ffth_result * nloads)()
+    st = load().ffth_solve_order2(plan, eps0_ptr, eps1_ptr, nloads, hp, eps_ptr, res)
+    return st, [r.as_dict() for r in res]
+
+
+def ffth_order2_rhs(plan, eps0_ptr, eps1_ptr, H, p_ptr):
+    h, hp = _darr(H)
+    gm = (ctypes.c_double * 3)()
+    _check(load().ffth_order2_rhs(plan, eps0_ptr, eps1_ptr, hp, p_ptr, gm), "ffth_order2_rhs")
+    return list(gm)
+
+
 def ffth_profile_enable(plan, on=True):
     _check(load().ffth_profile_enable(plan, 1 if on else 0), "ffth_profile_enable")
 
@@ -327,6 +347,22 @@ class Solver:
         u = self.torch.empty((3,) + self.n, dtype=self.torch.float64, device=self.device)
         ffth_displacement(self.plan, _dptr(eps), _dptr(u))
         return u
+
+    def solve_order2(self, eps0_six, eps1_18, H, out=None, check=True):
+        H = np.asarray(H, dtype=np.float64).reshape(-1, 54)
+        nl = H.shape[0]
+        eps = out if out is not None else self.field(6, nl)
+        st, res = ffth_solve_order2(self.plan, _dptr(eps0_six.contiguous()), _dptr(eps1_18.contiguous()), H,
+                                    _dptr(eps), nl)
+        if check:
+            _check(st, "ffth_solve_order2")
+        return eps, res
+
+    def order2_rhs(self, eps0_six, eps1_18, H):
+        p = self.torch.empty((6,) + self.n, dtype=self.torch.float64, device=self.device)
+        gm = ffth_order2_rhs(self.plan, _dptr(eps0_six.contiguous()), _dptr(eps1_18.contiguous()),
+                             np.asarray(H, np.float64).reshape(54), _dptr(p))
+        return p, gm
 
     def order1_rhs(self, eps0_six, G):
         p = self.torch.empty((6,) + self.n, dtype=self.torch.float64, device=self.device)

@@ -1,0 +1,108 @@
+"""GPU parity of the problem of the paper's order alpha = 3 ("order 2"):
+right-hand side from the order-0 correctors and the 18 order-1 unit-gradient
+solutions, its solve, and the whole order 0 -> 1 -> 2 chain on the GPU."""
+import numpy as np
+import pytest
+
+from oracle import homogenization as H
+from paper_1712_05145_amd import ffth
+from paper_1712_05145_amd import microstructure as M
+from tests._gpu import rel_l2, require_gpu, to_dev, voigt6
+
+pytestmark = pytest.mark.gpu
+
+
+def _hessian(seed):
+    h = np.random.default_rng(seed).standard_normal((6, 3, 3))
+    return 0.5 * (h + np.swapaxes(h, 1, 2))
+
+
+@pytest.fixture(scope="module")
+def random_case():
+    """Random two-phase voxels (no symmetry), oracle chain up to order 2."""
+    shape = (8, 6, 12)
+    phase = M.random_phases(shape, 2, 21)
+    lame = M.lame_from_young([1.0, 7.0], [0.3, 0.25])
+    lam0, mu0 = M.midpoint_reference(lame)
+    prob = H.make_problem(phase, lam0, mu0, lame=lame)
+    _, corr, _ = H.effective_stiffness(prob, "cg", tol=1e-13)
+    sols, means = H.order1_unit_solutions(prob, corr, tol=1e-13)
+    return phase, lame, lam0, mu0, prob, corr, sols, means
+
+
+def test_order2_rhs_parity(random_case):
+    torch = require_gpu()
+    print("case order2 rhs", flush=True)
+    phase, lame, lam0, mu0, prob, corr, sols, _ = random_case
+    hess = _hessian(3)
+    p_ref, p3, theta, g, gmean = H.order2_rhs(prob, corr, sols, hess)
+    eps0 = to_dev(torch, np.stack([voigt6(c) for c in corr]))
+    eps1 = to_dev(torch, np.stack([voigt6(s) for s in sols]))
+    s = ffth.Solver(phase, lam0, mu0, lame=lame, order=2, nloads=1)
+    pg, gm = s.order2_rhs(eps0, eps1, hess.reshape(54))
+    assert rel_l2(pg.cpu().numpy(), voigt6(p_ref)) < 1e-12
+    assert np.allclose(gm, gmean, rtol=1e-11, atol=1e-12 * np.abs(gmean).max())
+
+
+@pytest.mark.parametrize("scheme,precision", [("cg", "fp64"), ("cg", "mixed"), ("bicgstab", "fp64")])
+def test_order2_solve_parity(random_case, scheme, precision):
+    torch = require_gpu()
+    print("case order2 solve", scheme, precision, flush=True)
+    phase, lame, lam0, mu0, prob, corr, sols, _ = random_case
+    hess = np.stack([_hessian(4), _hessian(5)])
+    refs = [H.solve_order2(prob, corr, sols, h, "cg", tol=1e-13) for h in hess]
+    eps0 = to_dev(torch, np.stack([voigt6(c) for c in corr]))
+    eps1 = to_dev(torch, np.stack([voigt6(s) for s in sols]))
+    s = ffth.Solver(phase, lam0, mu0, lame=lame, order=2, nloads=2, scheme=scheme, precision=precision,
+                    tol=1e-10)
+    eps3, res = s.solve_order2(eps0, eps1, hess.reshape(2, 54))
+    eps3 = eps3.cpu().numpy()
+    for l in range(2):
+        eref, info = refs[l]
+        assert res[l]["status"] == 0
+        assert rel_l2(eps3[l], voigt6(eref)) < 1e-6
+        ms = np.asarray(info["mean_stress"])
+        assert np.allclose(res[l]["mean_stress"], ms, rtol=1e-6, atol=1e-8 * np.abs(ms).max())
+        assert np.allclose(res[l]["g_mean"], info["g_mean"], rtol=1e-10, atol=1e-12)
+
+
+def test_order2_chain_on_gpu(random_case):
+    """Order 0 (six loads), order 1 (the 18 unit gradient loads in one batched
+    call) and order 2 all on the GPU, against the oracle's chain."""
+    torch = require_gpu()
+    print("case order2 chain", flush=True)
+    phase, lame, lam0, mu0, prob, corr, sols, means = random_case
+    s0 = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, tol=1e-11)
+    eps0, _ = s0.solve_order0(np.eye(6))
+    s1 = ffth.Solver(phase, lam0, mu0, lame=lame, order=1, nloads=18, tol=1e-11)
+    eps1, r1 = s1.solve_order1(eps0, np.eye(18))
+    for k in range(18):
+        assert rel_l2(eps1[k].cpu().numpy(), voigt6(sols[k])) < 1e-6
+        ms = means[k]
+        assert np.allclose(r1[k]["mean_stress"], ms, rtol=1e-6, atol=1e-8 * max(1.0, np.abs(ms).max()))
+    hess = _hessian(6)
+    eref, info = H.solve_order2(prob, corr, sols, hess, "cg", tol=1e-13)
+    s2 = ffth.Solver(phase, lam0, mu0, lame=lame, order=2, nloads=1, tol=1e-10)
+    eps3, res = s2.solve_order2(eps0, eps1, hess.reshape(1, 54))
+    assert rel_l2(eps3[0].cpu().numpy(), voigt6(eref)) < 1e-5
+
+
+def test_order2_homogeneous_zero():
+    torch = require_gpu()
+    n = (8, 8, 8)
+    phase = np.zeros(n, dtype=np.uint16)
+    s = ffth.Solver(phase, 2.0, 1.0, lame=[[1.0, 0.7]], order=2, nloads=1)
+    eps0 = torch.zeros((6, 6) + n, dtype=torch.float64, device="cuda")
+    eps1 = torch.zeros((18, 6) + n, dtype=torch.float64, device="cuda")
+    eps3, res = s.solve_order2(eps0, eps1, _hessian(7).reshape(1, 54))
+    assert res[0]["iters"] == 0 and torch.count_nonzero(eps3).item() == 0
+
+
+def test_order2_rejects_plan_of_other_order():
+    torch = require_gpu()
+    phase = np.zeros((8, 8, 8), dtype=np.uint16)
+    s = ffth.Solver(phase, 2.0, 1.0, lame=[[1.0, 0.7]], order=1, nloads=1)
+    z0 = torch.zeros((6, 6, 8, 8, 8), dtype=torch.float64, device="cuda")
+    z1 = torch.zeros((18, 6, 8, 8, 8), dtype=torch.float64, device="cuda")
+    with pytest.raises(ffth.FFTHError):
+        s.solve_order2(z0, z1, np.zeros((1, 54)))

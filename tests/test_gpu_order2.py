@@ -106,3 +106,40 @@ def test_order2_rejects_plan_of_other_order():
     z1 = torch.zeros((18, 6, 8, 8, 8), dtype=torch.float64, device="cuda")
     with pytest.raises(ffth.FFTHError):
         s.solve_order2(z0, z1, np.zeros((1, 54)))
+
+
+def test_effective_tensors_against_oracle(random_case):
+    """The effective stiffness, the third-order tensor of the 18 unit gradient
+    loads and the order-2 tensor equal the oracle's averages."""
+    torch = require_gpu()
+    print("case effective tensors", flush=True)
+    from paper_1712_05145_amd.effective import SECOND_PAIRS, effective_tensors, second_gradient_unit
+    phase, lame, lam0, mu0, prob, corr, sols, means = random_case
+    ceff, _, _ = H.effective_stiffness(prob, "cg", tol=1e-13)
+    t = effective_tensors(phase, lam0, mu0, lame=lame, order=2, precision="fp64", tol=1e-11)
+    d = np.sqrt(np.outer(np.diag(ceff), np.diag(ceff)))
+    assert np.all(np.abs(t["C"] - ceff) <= 1e-8 * d)
+    scale = np.abs(means).max()
+    assert np.abs(t["B"] - means.T).max() < 1e-7 * scale
+    # <g> of the unit gradient loads is a contraction of C's columns
+    expect = np.zeros((3, 18))
+    for J in range(6):
+        s = np.array([[ceff[0, J], ceff[5, J], ceff[4, J]], [ceff[5, J], ceff[1, J], ceff[3, J]],
+                      [ceff[4, J], ceff[3, J], ceff[2, J]]])
+        for j in range(3):
+            expect[:, J * 3 + j] = (1.0 if J < 3 else 2.0) * s[:, j]
+    assert np.abs(t["gB"] - expect).max() < 1e-8 * np.abs(expect).max()
+    for k in (0, 7, 20, 35):
+        _, info = H.solve_order2(prob, corr, sols, second_gradient_unit(k).reshape(6, 3, 3), "cg", tol=1e-13)
+        ms = np.asarray(info["mean_stress"])
+        assert np.allclose(t["D"][:, k], ms, rtol=1e-6, atol=1e-7 * max(1.0, np.abs(ms).max())), SECOND_PAIRS[k]
+
+
+def test_third_order_tensor_vanishes_for_centrosymmetric_cell():
+    """A centred sphere is symmetric under y -> -y: the strain-gradient tensor B is zero."""
+    torch = require_gpu()
+    from paper_1712_05145_amd.effective import effective_tensors
+    phase, lame = M.centred_sphere(16, young=(1.0, 20.0))
+    lam0, mu0 = M.midpoint_reference(lame)
+    t = effective_tensors(phase, lam0, mu0, lame=lame, order=1, precision="fp64", tol=1e-11)
+    assert np.abs(t["B"]).max() < 1e-9 * np.abs(t["C"]).max()

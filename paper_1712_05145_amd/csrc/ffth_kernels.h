@@ -55,9 +55,10 @@ template <typename T> constexpr int z_cols(int n) {
 }
 // Candidate shapes for the runtime autotuner: variant 0 is the measured
 // default above, 1 and 2 halve / double the tile (or swap the block size of
-// the y-pass), within 96 KB of LDS per block; 3 keeps the tile of 0 with fewer
-// threads per block (x: one wave, z: two), for lengths whose Stockham stages
-// have fewer butterflies than the default block has threads.
+// the y-pass), within 96 KB of LDS per block; 3 keeps the x tile of 0 with one
+// wave per block (lengths whose Stockham stages have fewer butterflies than
+// the default block has threads) and gives the z-pass three times the columns
+// with 512 threads (rows of >= 144 contiguous bytes).
 template <typename T> constexpr int lds_cap_rows(int n) {          // x-pass rows within 96 KB
   int r = 98304 / (3 * (n + n / 16) * (int)(2 * sizeof(T)));
   return r < 1 ? 1 : pow2_floor(r);
@@ -75,13 +76,13 @@ template <typename T> constexpr int y_cols_v(int n, int v) {
   return c;
 }
 template <typename T> constexpr int x_threads_v(int, int v) { return v == 3 ? 64 : NT; }
-template <typename T> constexpr int z_threads_v(int, int v) { return v == 3 ? 128 : NT; }
+template <typename T> constexpr int z_threads_v(int, int v) { return v == 3 ? 512 : NT; }
 template <typename T> constexpr int y_threads_v(int n, int v) {
   return v == 1 ? (y_threads<T>(n) == 512 ? 256 : 512) : v == 2 ? 256 : y_threads<T>(n);
 }
 template <typename T> constexpr int z_cols_v(int n, int v) {
   int c = z_cols<T>(n);
-  c = v == 1 ? 2 * c : v == 2 ? (c > 1 ? c / 2 : 1) : c;
+  c = v == 1 ? 2 * c : v == 2 ? (c > 1 ? c / 2 : 1) : v == 3 ? 3 * c : c;
   const int cap = 98304 / (n * 6 * (int)(2 * sizeof(T)));
   c = c > cap ? (cap < 1 ? 1 : pow2_floor(cap)) : c;
   return c;

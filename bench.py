@@ -30,19 +30,32 @@ HBM_PEAK_GBS = 8000.0
 
 # Algorithmic HBM bytes per voxel for one load in one launch of the FP32
 # kernel categories whose traffic does not depend on the mode (4-byte words,
-# 2-byte phase ids; the half spectrum is 6 x n/2 complex = 24 B per voxel):
+# 2-byte phase ids; the half spectrum is 6 x n/2 complex = 24 B per voxel in
+# FP32, 12 B in binary16):
 #   y-pass / z-pass        spectrum read and written                 24+24
 #   fused three-term CG    spectrum, r_k, x_k, r_k-1, x_k-1, phase read;
 #   x-pass                 r_k+1, x_k+1, spectrum written            24*5+2+24*3
 #   start pass of a solve  r_0, phase read; spectrum written          24+2+24
+# With the binary16 forward spectrum of the inner solve, every write of the
+# spectrum before the spectral operator and every read of it up to there is
+# 12 B: forward y-pass 12+12, z-pass 12+24, fused pass 24*5+2+24*2+12, start
+# pass 24+2+12; the inverse y-pass (24+24) and the projection passes stay FP32.
 # The first iteration of each inner solve reads neither x_k nor r_k-1, x_k-1
 # (x_0 = 0, omega = 1) and the second does not read x_k-1: per started solve
-# the fused kernel moves 72 + 24 B/voxel less than 194 per iteration.  The
+# the fused kernel moves 72 + 24 B/voxel less than a full iteration.  The
 # model subtracts both for every start (a lower bound on the bytes moved when
 # a solve stops after one iteration).  The FP32 x-forward / x-inverse
 # categories hold the projection passes only and are reported without a model.
-ALG_BYTES_F32 = {"ypass_f32": 48.0, "zpass_f32": 48.0, "xcg3_f32": 194.0, "cg3start_f32": 50.0}
+ALG_CATEGORIES = ("ypass_f32", "zpass_f32", "xcg3_f32", "cg3start_f32")
 XCG3_START_SAVING = 96.0
+
+
+def alg_bytes_per_voxel(h16):
+    """Bytes per voxel of (forward y, inverse y, z, fused CG pass, start pass)
+    in the inner solve; projection passes move 48 B in each y- and z-pass."""
+    if h16:
+        return {"yf": 24.0, "yi": 48.0, "z": 36.0, "xcg3": 182.0, "start": 38.0}
+    return {"yf": 48.0, "yi": 48.0, "z": 48.0, "xcg3": 194.0, "start": 50.0}
 
 
 def measured_traffic(cat):
@@ -153,6 +166,7 @@ def main():
     ap.add_argument("--serve-count", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=40.0)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
+    ap.add_argument("--no-spectrum16", action="store_true", help="keep the inner solve's spectrum in FP32")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -178,7 +192,8 @@ def main():
     def make(precision, order, nloads, scheme=None):
         return ffth.Solver(phase, lam0, mu0, lame=lame, nloads=nloads, order=order, scheme=scheme or args.scheme,
                            precision=precision, tol=args.tol, max_iter=50000, inner_tol=args.inner_tol, max_outer=30,
-                           check_every=8, autotune=not args.no_autotune, device=dev)
+                           check_every=8, autotune=not args.no_autotune, spectrum16=not args.no_spectrum16,
+                           device=dev)
 
     # achievable streaming bandwidth on this device (context for the roofline)
     buf_a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -246,13 +261,18 @@ def main():
     real_units = {"xcg3_f32": inner, "ypass_f32": 2 * (inner + proj), "zpass_f32": inner + proj}
     prof = {k: (v[0], v[1], real_units.get(k, v[2])) for k, v in prof.items()}
 
-    def alg_bytes(c, u):
-        b = ALG_BYTES_F32[c] * nvox * u
-        if c == "xcg3_f32":
-            b -= XCG3_START_SAVING * nvox * starts
-        return b
+    ab = alg_bytes_per_voxel(not args.no_spectrum16)
 
-    cat = max(ALG_BYTES_F32, key=lambda c: prof[c][1])
+    def alg_bytes(c, u):
+        if c == "ypass_f32":
+            return nvox * (inner * (ab["yf"] + ab["yi"]) + proj * 96.0)
+        if c == "zpass_f32":
+            return nvox * (inner * ab["z"] + proj * 48.0)
+        if c == "xcg3_f32":
+            return nvox * (inner * ab["xcg3"] - XCG3_START_SAVING * starts)
+        return nvox * ab["start"] * u
+
+    cat = max(ALG_CATEGORIES, key=lambda c: prof[c][1])
     launches, tot_ms, units = prof[cat]
     bytes_total = alg_bytes(cat, units)
     achieved = bytes_total / (tot_ms * 1e-3) / 1e9 if tot_ms > 0 else 0.0
@@ -262,7 +282,7 @@ def main():
         entry = {"launches": n_l, "loads": u, "total_ms": round(ms, 3),
                  "avg_ms": round(ms / n_l, 4) if n_l else None,
                  "ms_per_load": round(ms / u, 4) if u else None}
-        if c in ALG_BYTES_F32 and ms > 0:
+        if c in ALG_CATEGORIES and ms > 0:
             entry["alg_bytes_per_voxel_per_load"] = round(alg_bytes(c, u) / (nvox * u), 2)
             entry["achieved_GBs"] = round(alg_bytes(c, u) / (ms * 1e-3) / 1e9, 1)
         kernels[c] = entry

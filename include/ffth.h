@@ -102,6 +102,14 @@ typedef struct {
   int32_t check_every;        /* iterations between host reads of the convergence flags */
   int32_t autotune;           /* 1: time the compiled tile shapes of every pass at plan
                                  creation (grids >= 64^3) and keep the fastest          */
+  int32_t spectrum16;         /* MIXED CG: 1 keeps the FP32 inner solve's spectrum in
+                                 binary16 from the forward transforms up to the Green
+                                 operator (FP32 arithmetic, scaled into range; FP32
+                                 after the operator), on grids of at least
+                                 FFTH_SPECTRUM16_MIN_VOXELS voxels whose stiffness
+                                 contrast (ffth_stiffness_contrast) is at most
+                                 FFTH_SPECTRUM16_MAX_CONTRAST; 0: FP32 throughout.
+                                 The FP64 defect correction sets the final accuracy    */
 } ffth_opts;
 
 typedef struct {
@@ -122,8 +130,24 @@ typedef struct {
 typedef struct ffth_plan ffth_plan;
 
 /* Default options: CG, MIXED, tol 1e-8, max_iter 20000, inner_tol 1e-2,
- * max_outer 30, check_every 8, autotune 1. */
+ * max_outer 30, check_every 8, autotune 1, spectrum16 1. */
 void ffth_default_opts(ffth_opts *o);
+
+/* Stiffness contrast of the phases of a problem (Sec. 2's stiffness table):
+ * the largest eigen-modulus over the smallest, across all phases, where the
+ * eigen-moduli of a phase are the eigenvalues of its stiffness in Mandel form
+ * (Voigt matrix with the shear rows and columns scaled by sqrt 2; 3 lambda +
+ * 2 mu and five times 2 mu for isotropic phases).  lame: HOST nphases x 2, or
+ * NULL and stiffness: HOST nphases x 21 Voigt upper triangle.  Returns
+ * INFINITY when a phase is not positive definite, and NAN for bad arguments
+ * (nphases < 1, both tables NULL).  Host only; no device is touched.
+ * Binary16 rounding (unit 2^-11) times this contrast bounds the relative error
+ * a binary16 spectrum adds to the inner operator; above the limit below a
+ * MIXED CG plan keeps its spectrum in FP32 whatever spectrum16 says. */
+#define FFTH_SPECTRUM16_MAX_CONTRAST 400.0
+/* Smaller grids are bound by launch latency, where binary16 saves nothing. */
+#define FFTH_SPECTRUM16_MIN_VOXELS 2097152
+double ffth_stiffness_contrast(int32_t nphases, const double *lame, const double *stiffness);
 
 /* 1 if n (one axis length) is supported by the compiled FFT kernels
  * (4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 256, 512, 1024).  Axis 0 may

@@ -175,6 +175,21 @@ template <typename T, int N, int NT> __device__ __forceinline__ void build_twidd
 // ---------------------------------------------------------------------------
 template <bool PADDED> __device__ __forceinline__ int padx(int e) { return PADDED ? e + (e >> 4) : e; }
 
+// Spectrum values in global memory: full-precision complex, or a pair of
+// binary16 values (round to nearest on store, exact widening on load).
+struct H2 {
+  _Float16 x, y;
+};
+template <typename T> __device__ __forceinline__ C2<T> sload(const C2<T>* p) { return *p; }
+template <typename T> __device__ __forceinline__ C2<T> sload(const H2* p) {
+  const H2 h = *p;
+  return C2<T>{(T)h.x, (T)h.y};
+}
+template <typename T> __device__ __forceinline__ void sstore(C2<T>* p, const C2<T>& v) { *p = v; }
+template <typename T> __device__ __forceinline__ void sstore(H2* p, const C2<T>& v) {
+  *p = H2{(_Float16)v.x, (_Float16)v.y};
+}
+
 // Two adjacent complex values moved with one 16-byte access (FP32 layouts in
 // which consecutive sequences are adjacent in memory).
 template <typename T> struct alignas(16) Pair { C2<T> a, b; };

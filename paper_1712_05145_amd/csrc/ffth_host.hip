@@ -133,7 +133,67 @@ void iso_to_m(double lam, double mu, double m[36]) {
   for (int a = 3; a < 6; ++a) m[a * 6 + a] = 2.0 * mu;
 }
 
+// Eigenvalues of a symmetric 6 x 6 matrix (cyclic Jacobi rotations).
+void sym6_eigenvalues(double a[6][6], double ev[6]) {
+  for (int sweep = 0; sweep < 50; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < 6; ++i)
+      for (int j = 0; j < 6; ++j) (i == j ? tot : off) += a[i][j] * a[i][j];
+    if (off <= 1e-30 * (tot + off)) break;
+    for (int p = 0; p < 5; ++p) {
+      for (int q = p + 1; q < 6; ++q) {
+        if (a[p][q] == 0.0) continue;
+        const double th = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);
+        const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+        const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+        for (int k = 0; k < 6; ++k) {   // A <- A J
+          const double akp = a[k][p], akq = a[k][q];
+          a[k][p] = c * akp - s * akq;
+          a[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < 6; ++k) {   // A <- J^T A
+          const double apk = a[p][k], aqk = a[q][k];
+          a[p][k] = c * apk - s * aqk;
+          a[q][k] = s * apk + c * aqk;
+        }
+      }
+    }
+  }
+  for (int i = 0; i < 6; ++i) ev[i] = a[i][i];
+}
+
+// Stiffness contrast of the phases: the largest eigen-modulus (eigenvalue of
+// the stiffness in Mandel form) over the smallest, across all phases; infinite
+// when a phase is not positive definite.  Isotropic phases have 3 lambda + 2 mu
+// (once) and 2 mu (five times).
+double stiffness_contrast(int nph, bool iso, const double* lame, const double* v21) {
+  double lo = INFINITY, hi = 0.0;
+  for (int ph = 0; ph < nph; ++ph) {
+    double ev[6];
+    if (iso) {
+      const double lam = lame[2 * ph], mu = lame[2 * ph + 1];
+      ev[0] = 3.0 * lam + 2.0 * mu;
+      for (int i = 1; i < 6; ++i) ev[i] = 2.0 * mu;
+    } else {
+      double a[6][6];
+      int k = 0;
+      for (int r = 0; r < 6; ++r)
+        for (int c = r; c < 6; ++c) {
+          const double w = (r < 3 ? 1.0 : std::sqrt(2.0)) * (c < 3 ? 1.0 : std::sqrt(2.0));
+          a[r][c] = a[c][r] = v21[21 * ph + k++] * w;
+        }
+      sym6_eigenvalues(a, ev);
+    }
+    for (int i = 0; i < 6; ++i) {
+      lo = std::min(lo, ev[i]);
+      hi = std::max(hi, ev[i]);
+    }
+  }
+  return lo > 0.0 ? hi / lo : INFINITY;
+}
+
 }  // namespace
+
 
 struct ffth_plan {
   int n[3];
@@ -143,6 +203,9 @@ struct ffth_plan {
   int nph;
   bool iso;
   double lam0, mu0;
+  bool h16 = false;    // the mixed scheme's FP32 inner solve keeps its spectrum in binary16
+  double kappa = 1.0;  // max row sum of |C - C0| / mu0 over the phases (range of the polarization)
+  double contrast = 1.0;  // largest over smallest eigen-modulus of the phases
   const uint16_t* phase;
   hipStream_t stream;
   int nloads;
@@ -270,6 +333,9 @@ Desc base_desc(ffth_plan* P, int l) {
   d.lam0 = P->lam0;
   d.mu0 = P->mu0;
   d.nc = 6;
+  d.inv_nvox = 1.0 / (double)P->nvox;
+  d.tau_scale = 1.0;
+  d.op_scale = 1.0 / (double)P->nvox;
   return d;
 }
 
@@ -283,6 +349,7 @@ SolverState make_state(double tol, int max_iter, double guard_eps, int active) {
   s.active = active;
   s.first = 1;
   s.res = 1.0;
+  s.dscale = 1.0;
   return s;
 }
 
@@ -317,9 +384,9 @@ template <typename T> int pv(ffth_plan* P, Pass ps) { return P->var[ps][sizeof(T
 template <typename T> int xblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->nx64 : P->nx32; }
 template <typename T> int iblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->ni64 : P->ni32; }
 
-template <typename T> ffth_status xfwd(ffth_plan* P, const Desc* d, int nb, int mode) {
+template <typename T> ffth_status xfwd(ffth_plan* P, const Desc* d, int nb, int mode, bool h16 = false) {
   ProfScope ps(P, sizeof(T) == 8 ? C_XF64 : mode == XF_R3 ? C_CG3S : C_XF32, nb);
-  HIPCHK(Launch<T>::xfwd(P->n[2], P->iso, pv<T>(P, PS_XF), dim3(xblocks<T>(P), nb), P->stream, d, mode, P->rows,
+  HIPCHK(Launch<T>::xfwd(P->n[2], P->iso, pv<T>(P, PS_XF), h16, dim3(xblocks<T>(P), nb), P->stream, d, mode, P->rows,
                          P->nvox));
   return FFTH_OK;
 }
@@ -332,7 +399,7 @@ int kchunk_host(int h) {
   return c;
 }
 
-template <typename T> ffth_status yzy(ffth_plan* P, const Desc* d, int nb, int op) {
+template <typename T> ffth_status yzy(ffth_plan* P, const Desc* d, int nb, int op, bool h16 = false) {
   const int kc = kchunk_host(P->h);
   const int ncols = kc * 6;
   const int nplanes = P->n[0] * (P->h / kc);
@@ -342,7 +409,7 @@ template <typename T> ffth_status yzy(ffth_plan* P, const Desc* d, int nb, int o
   const int cy = sizeof(T) == 8 ? C_Y64 : C_Y32, cz = sizeof(T) == 8 ? C_Z64 : C_Z32;
   {
     ProfScope ps(P, cy, nb);
-    HIPCHK(Launch<T>::ypass(P->n[1], vy, dim3(nplanes * ntiles, nb), P->stream, d, -1, ncols, ntiles));
+    HIPCHK(Launch<T>::ypass(P->n[1], vy, h16, dim3(nplanes * ntiles, nb), P->stream, d, -1, ncols, ntiles));
   }
   const long M = (long)P->n[1] * kc;
   const int tk = Launch<T>::z_cols(P->n[0], vz);
@@ -350,11 +417,12 @@ template <typename T> ffth_status yzy(ffth_plan* P, const Desc* d, int nb, int o
   {
     ProfScope ps(P, cz, nb);
     const int nzb = (int)((M + tk - 1) / tk) * (P->h / kc);
-    HIPCHK(Launch<T>::zpass(P->n[0], vz, dim3(nzb, nb), P->stream, d, op, P->n[1], P->h, scale));
+    HIPCHK(Launch<T>::zpass(P->n[0], vz, h16, dim3(nzb, nb), P->stream, d, op, P->n[1], P->h, scale));
   }
   {
     ProfScope ps(P, cy, nb);
-    HIPCHK(Launch<T>::ypass(P->n[1], vy, dim3(nplanes * ntiles, nb), P->stream, d, +1, ncols, ntiles));
+    // the inverse y-transform reads the FP32 copy of a binary16 inner solve
+    HIPCHK(Launch<T>::ypass(P->n[1], vy, false, dim3(nplanes * ntiles, nb), P->stream, d, +1, ncols, ntiles));
   }
   return FFTH_OK;
 }
@@ -376,7 +444,7 @@ ffth_status fin(ffth_plan* P, const Desc* d, int nb, int op, int nblk_f, int nbl
 ffth_status cg3_start(ffth_plan* P, const Desc* d, int nb) {
   ffth_status s;
   if (nb <= 0) return FFTH_OK;
-  if ((s = xfwd<float>(P, d, nb, XF_R3)) != FFTH_OK) return s;
+  if ((s = xfwd<float>(P, d, nb, XF_R3, P->h16)) != FFTH_OK) return s;
   return fin(P, d, nb, FIN_CG3_INIT, xblocks<float>(P), 0);
 }
 
@@ -384,10 +452,10 @@ ffth_status cg3_start(ffth_plan* P, const Desc* d, int nb) {
 ffth_status cg3_iter(ffth_plan* P, const Desc* d, int nb) {
   ffth_status s;
   if (nb <= 0) return FFTH_OK;
-  if ((s = yzy<float>(P, d, nb, OP_GAMMA)) != FFTH_OK) return s;
+  if ((s = yzy<float>(P, d, nb, OP_GAMMA, P->h16)) != FFTH_OK) return s;
   {
     ProfScope ps(P, C_XCG3, nb);
-    HIPCHK(Launch<float>::xcg3(P->n[2], P->iso, pv<float>(P, PS_XI), dim3(iblocks<float>(P), nb), P->stream, d,
+    HIPCHK(Launch<float>::xcg3(P->n[2], P->iso, pv<float>(P, PS_XI), P->h16, dim3(iblocks<float>(P), nb), P->stream, d,
                                P->rows, P->nvox));
   }
   return fin(P, d, nb, FIN_CG3, 0, iblocks<float>(P));
@@ -401,7 +469,7 @@ ffth_status cg3_iter(ffth_plan* P, const Desc* d, int nb) {
 // Choices are cached per (grid, material kind, precision, scheme) for the
 // process.  Grids below 64^3 keep the defaults (launch-bound).
 std::mutex g_tune_mu;
-std::map<std::array<int, 6>, std::array<int, 8>> g_tune_cache;
+std::map<std::array<int, 7>, std::array<int, 8>> g_tune_cache;
 
 template <class F> double time_launches(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F&& launch) {
   launch();  // warm-up
@@ -420,7 +488,7 @@ template <class F> double time_launches(hipStream_t st, hipEvent_t e0, hipEvent_
   return ms / reps;
 }
 
-template <typename T> void tune_prec(ffth_plan* P, const Desc* d, int xf_mode, int xi_mode, bool fused) {
+template <typename T> void tune_prec(ffth_plan* P, const Desc* d, int xf_mode, int xi_mode, bool fused, bool h16) {
   const int pi = sizeof(T) == 8 ? 1 : 0;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return;
@@ -440,23 +508,27 @@ template <typename T> void tune_prec(ffth_plan* P, const Desc* d, int xf_mode, i
       double t;
       if (pass == PS_XF) {
         t = time_launches(P->stream, e0, e1, [&] {
-          (void)Launch<T>::xfwd(P->n[2], P->iso, v, dim3(xblocks<T>(P), 1), P->stream, d, xf_mode, P->rows, P->nvox);
+          (void)Launch<T>::xfwd(P->n[2], P->iso, v, h16, dim3(xblocks<T>(P), 1), P->stream, d, xf_mode, P->rows,
+                                P->nvox);
         });
       } else if (pass == PS_Y) {
         const int cw = Launch<T>::y_cols(P->n[1], v), nt = (ncols + cw - 1) / cw;
+        // binary16 forward spectrum: the variant serves the binary16 forward and
+        // the FP32 inverse transform, so both are timed together
         t = time_launches(P->stream, e0, e1, [&] {
-          (void)Launch<T>::ypass(P->n[1], v, dim3(nplanes * nt, 1), P->stream, d, -1, ncols, nt);
+          (void)Launch<T>::ypass(P->n[1], v, h16, dim3(nplanes * nt, 1), P->stream, d, -1, ncols, nt);
+          if (h16) (void)Launch<T>::ypass(P->n[1], v, false, dim3(nplanes * nt, 1), P->stream, d, +1, ncols, nt);
         });
       } else if (pass == PS_Z) {
         const int tk = Launch<T>::z_cols(P->n[0], v);
         const int nzb = (int)((M + tk - 1) / tk) * (P->h / kc);
         t = time_launches(P->stream, e0, e1, [&] {
-          (void)Launch<T>::zpass(P->n[0], v, dim3(nzb, 1), P->stream, d, OP_GAMMA, P->n[1], P->h,
+          (void)Launch<T>::zpass(P->n[0], v, h16, dim3(nzb, 1), P->stream, d, OP_GAMMA, P->n[1], P->h,
                                  1.0 / (double)P->nvox);
         });
       } else if (fused) {
         t = time_launches(P->stream, e0, e1, [&] {
-          (void)Launch<T>::xcg3(P->n[2], P->iso, v, dim3(iblocks<T>(P), 1), P->stream, d, P->rows, P->nvox);
+          (void)Launch<T>::xcg3(P->n[2], P->iso, v, h16, dim3(iblocks<T>(P), 1), P->stream, d, P->rows, P->nvox);
         });
       } else {
         t = time_launches(P->stream, e0, e1, [&] {
@@ -475,10 +547,21 @@ template <typename T> void tune_prec(ffth_plan* P, const Desc* d, int xf_mode, i
   (void)hipEventDestroy(e1);
 }
 
+// Inner-solve descriptor with a binary16 forward spectrum: tau / (kappa mu0 n2)
+// before the x-transform, the forward y-transform divided by n1, and
+// kappa mu0 / n0 in the spectral operator, whose FP32 output goes to spec2
+// (placed after the binary16 spectrum inside the load's spectrum region).
+void set_h16(const ffth_plan* P, Desc& d) {
+  d.h16 = 1;
+  d.spec2 = (char*)d.spec + al((size_t)P->nvox * 3 * sizeof(float));
+  d.tau_scale = 1.0 / (P->kappa * P->mu0 * (double)P->n[2]);
+  d.op_scale = P->kappa * P->mu0 / (double)P->n[0];
+}
+
 ffth_status autotune(ffth_plan* P) {
   const ffth_opts& o = P->opts;
   if (!o.autotune || P->nvox < 64L * 64 * 64) return FFTH_OK;
-  const std::array<int, 6> key{P->n[0], P->n[1], P->n[2], P->iso ? 1 : 0, o.precision, o.scheme};
+  const std::array<int, 7> key{P->n[0], P->n[1], P->n[2], P->iso ? 1 : 0, o.precision, o.scheme, P->h16 ? 1 : 0};
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune_cache.find(key);
@@ -519,8 +602,9 @@ ffth_status autotune(ffth_plan* P) {
       xf = XF_MATVEC;
       xi = XI_BS_INNER;
     }
+    if (fused && P->h16) set_h16(P, d);
     if ((s = upload_one(d)) != FFTH_OK) return s;
-    tune_prec<float>(P, dd, xf, xi, fused);
+    tune_prec<float>(P, dd, xf, xi, fused, fused && P->h16);
   }
   if (mixed || (o.precision == FFTH_FP64 && P->L.nf64 >= 2)) {   // FP64 passes
     Desc d = base_desc(P, 0);
@@ -539,7 +623,7 @@ ffth_status autotune(ffth_plan* P) {
       xi = XI_CG;
     }
     if ((s = upload_one(d)) != FFTH_OK) return s;
-    tune_prec<double>(P, dd, xf, xi, false);
+    tune_prec<double>(P, dd, xf, xi, false, false);
   }
   HIPCHK(hipStreamSynchronize(P->stream));
   HIPCHK(hipGetLastError());
@@ -701,13 +785,24 @@ ffth_status enter_inner(Job& J) {
   return FFTH_OK;
 }
 
-// One round for a group of mixed-precision jobs sharing grid size and material
-// kind (and stream).  Every job ends the round with its states read back.
+// One round for a group of mixed-precision jobs sharing grid size, material
+// kind and spectrum precision (and stream).  Every job ends the round with its
+// states read back.
 ffth_status group_round(std::vector<Job*>& jobs, Stage& st) {
   if (jobs.empty()) return FFTH_OK;
   ffth_plan* dims = jobs[0]->P;
   const ffth_opts& o = dims->opts;
   ffth_status s;
+  for (Job* J : jobs) {
+    // one launch serves every job: a binary16 kernel needs the FP32 copy
+    // (spec2) that only binary16 descriptors carry, and the tiles must agree
+    const ffth_plan* P = J->P;
+    if (P->n[0] != dims->n[0] || P->n[1] != dims->n[1] || P->n[2] != dims->n[2] || P->iso != dims->iso ||
+        P->h16 != dims->h16 || P->opts.scheme != o.scheme) {
+      g_last_error = "jobs of one round differ in grid, material kind, scheme or spectrum precision";
+      return FFTH_ERR_INVALID;
+    }
+  }
   int nA0 = 0, nA = 0, nPR = 0, nIN = 0, nFresh = 0;
   int kin = o.check_every;
   for (Job* J : jobs) {
@@ -863,6 +958,7 @@ void build_solve_descs(ffth_plan* P, int nl, const double* E, double* eps, bool 
         in.x1 = f32_ptr(P, l, 2);
         in.r1 = f32_ptr(P, l, 3);
       }
+      if (P->h16) set_h16(P, in);
     }
     P->h_desc[desc_slot(P, R_INNER, l)] = in;
     Desc post = base_desc(P, l);
@@ -997,9 +1093,15 @@ void ffth_default_opts(ffth_opts* o) {
   o->max_outer = 30;
   o->check_every = 8;
   o->autotune = 1;
+  o->spectrum16 = 1;
 }
 
 int32_t ffth_size_supported(int32_t n) { return size_supported(n) ? 1 : 0; }
+
+double ffth_stiffness_contrast(int32_t nphases, const double* lame, const double* stiffness) {
+  if (nphases < 1 || (!lame && !stiffness)) return NAN;
+  return stiffness_contrast(nphases, lame != nullptr, lame, stiffness);
+}
 
 size_t ffth_workspace_bytes(const int32_t n[3], int32_t nphases, int32_t nloads, int32_t order, const ffth_opts* o) {
   if (!n || !o || nloads < 1 || nphases < 1 || nphases > 65535 || order < 0 || order > 2) return 0;
@@ -1123,6 +1225,28 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
   }
   std::vector<float> m32(m64.size());
   for (size_t i = 0; i < m64.size(); ++i) m32[i] = (float)m64[i];
+  {
+    double kmax = 0.0;
+    for (int ph = 0; ph < p->nphases; ++ph) {
+      if (P->iso) {
+        kmax = std::max(kmax, 3.0 * std::fabs(m64[ph * 4 + 2]) + 2.0 * std::fabs(m64[ph * 4 + 3]));
+      } else {
+        for (int a = 0; a < 6; ++a) {
+          double rs = 0.0;
+          for (int b = 0; b < 6; ++b) rs += std::fabs(m64[ph * 72 + 36 + a * 6 + b]);
+          kmax = std::max(kmax, rs);
+        }
+      }
+    }
+    P->kappa = std::max(kmax / std::fabs(p->mu0), 1e-3);
+  }
+  // binary16 rounding (unit 2^-11) times the stiffness contrast bounds the
+  // relative error the stored spectrum adds to the inner solve's operator;
+  // above FFTH_SPECTRUM16_MAX_CONTRAST it would cost iterations, so FP32 is
+  // kept; below FFTH_SPECTRUM16_MIN_VOXELS the launches are latency-bound
+  P->contrast = stiffness_contrast(p->nphases, P->iso, p->lame, p->stiffness);
+  P->h16 = o->precision == FFTH_MIXED && o->scheme == FFTH_CG && o->spectrum16 != 0 &&
+           P->contrast <= FFTH_SPECTRUM16_MAX_CONTRAST && P->nvox >= FFTH_SPECTRUM16_MIN_VOXELS;
   bool ok = hip_ok(hipMemcpyAsync(P->mat64, m64.data(), m64.size() * 8, hipMemcpyHostToDevice, P->stream), "copy") &&
             hip_ok(hipMemcpyAsync(P->mat32, m32.data(), m32.size() * 4, hipMemcpyHostToDevice, P->stream), "copy");
   // phase ids must index the table
@@ -1677,9 +1801,11 @@ ffth_status ffth_server_step(ffth_server* S, int32_t* running, int32_t* waiting)
   if (!S) return FFTH_ERR_INVALID;
   ffth_status st = admit(S);
   if (st != FFTH_OK) return st;
-  // group running jobs by grid and material kind; one round per group
-  std::map<std::tuple<int, int, int, bool>, std::vector<Job*>> groups;
-  for (Request* r : S->running) groups[std::make_tuple(r->n[0], r->n[1], r->n[2], r->iso)].push_back(&r->job);
+  // group running jobs by grid, material kind and spectrum precision (the
+  // launches of a group take the first job's kernels); one round per group
+  std::map<std::tuple<int, int, int, bool, bool>, std::vector<Job*>> groups;
+  for (Request* r : S->running)
+    groups[std::make_tuple(r->n[0], r->n[1], r->n[2], r->iso, r->job.P->h16)].push_back(&r->job);
   for (auto& kv : groups) {
     std::vector<Job*>& all = kv.second;
     const int per = std::max(1, S->stage.cap / 6);

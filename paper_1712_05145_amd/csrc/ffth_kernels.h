@@ -19,6 +19,8 @@
 // All FFTs run in LDS (mixed-radix Stockham, fft_device.h).  Block tile
 // sizes are compile-time functions of the axis length and precision.
 #pragma once
+#include <type_traits>
+
 #include "fft_device.h"
 #include "ffth_types.h"
 
@@ -170,8 +172,8 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblk) {
 
 // After a forward FFT: unpack the two real transforms of each sequence and
 // store the half spectrum (k2 < N2/2) of the block's rows.
-template <typename T, int N2, int ROWS, int NTB>
-__device__ __forceinline__ void store_rows_r2c(C2<T>* spec, const C2<T>* z, long row0, long rows_total) {
+template <typename T, int N2, int ROWS, int NTB, typename S = C2<T>>
+__device__ __forceinline__ void store_rows_r2c(S* spec, const C2<T>* z, long row0, long rows_total) {
   constexpr int RS = N2 + N2 / 16;
   constexpr int H = N2 / 2;
   for (int v = threadIdx.x; v < ROWS * H * 6; v += NTB) {
@@ -185,14 +187,14 @@ __device__ __forceinline__ void store_rows_r2c(C2<T>* spec, const C2<T>* z, long
     C2<T> o;
     if ((c & 1) == 0) o = (z1 + z2) * T(0.5);
     else o = C2<T>{(z1.y - z2.y) * T(0.5), -(z1.x - z2.x) * T(0.5)};
-    spec[spec_at(row, k, c, rows_total, kchunk(H))] = o;
+    sstore<T>(spec + spec_at(row, k, c, rows_total, kchunk(H)), o);
   }
 }
 
 // Before an inverse FFT: load the half spectrum of the block's rows and
 // rebuild the full Hermitian-packed sequences (Nyquist bin zero).
-template <typename T, int N2, int ROWS, int NTB>
-__device__ __forceinline__ void load_rows_c2r(const C2<T>* spec, C2<T>* z, long row0, long rows_total) {
+template <typename T, int N2, int ROWS, int NTB, typename S = C2<T>>
+__device__ __forceinline__ void load_rows_c2r(const S* spec, C2<T>* z, long row0, long rows_total) {
   constexpr int RS = N2 + N2 / 16;
   constexpr int H = N2 / 2;
   for (int v = threadIdx.x; v < ROWS * H * 3; v += NTB) {
@@ -201,9 +203,9 @@ __device__ __forceinline__ void load_rows_c2r(const C2<T>* spec, C2<T>* z, long 
     const long row = row0 + rr;
     C2<T> a = {0, 0}, b = {0, 0};
     if (row < rows_total) {
-      const C2<T>* s = spec + spec_at(row, k, 2 * q, rows_total, kchunk(H));
-      a = s[0];
-      b = s[1];
+      const S* s = spec + spec_at(row, k, 2 * q, rows_total, kchunk(H));
+      a = sload<T>(s);
+      b = sload<T>(s + 1);
     }
     C2<T>* zr = z + (rr * 3 + q) * RS;
     if (k == 0) {
@@ -216,7 +218,7 @@ __device__ __forceinline__ void load_rows_c2r(const C2<T>* spec, C2<T>* z, long 
   }
 }
 
-template <typename T, int N2, bool ISO, int ROWS = x_rows<T>(N2), int NTB = NT>
+template <typename T, int N2, bool ISO, int ROWS = x_rows<T>(N2), int NTB = NT, typename S = C2<T>>
 __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, int mode, long rows_total,
                                               long nvox) {
   constexpr int RS = N2 + N2 / 16;
@@ -230,6 +232,7 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
   const T* mat = mat_of<T>(d);
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
   const T beta = (T)d.st->beta;
+  const T ts = d.h16 ? (T)(d.tau_scale / d.st->dscale) : T(1);   // binary16 spectrum scale
   const bool first = d.st->first != 0;
   // correction fused into the FP64 residual pass: with a three-term inner CG it
   // sits in the slot of the inner iteration count's parity (none after 0 iterations)
@@ -298,6 +301,8 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
       } else if (mode == XF_R3) {
         // start of the three-term CG: tau = (C - C0) r_0 and the sums
         // <r, r>_C0, <r, C r> (= <r, A r>_C0 on compatible r) and ||r||^2
+        // (binary16 spectrum: tau carries the factor that keeps the transforms
+        // in range, with the right-hand side's RMS divided out)
         const T* rp = (const T*)((d.st->iters & 1) ? d.r1 : d.r);
         T r[6], cr[6];
         double rd[6];
@@ -308,6 +313,10 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
         }
         apply_mat<T, ISO>(mat, ph, true, r, tau);
         apply_mat<T, ISO>(mat, ph, false, r, cr);
+        if (d.h16) {
+#pragma unroll
+          for (int c = 0; c < 6; ++c) tau[c] *= ts;
+        }
         acc0 += c0_ip(d.lam0, d.mu0, rd, rd);
         acc1 += (double)frob_w(r, cr);
         acc2 += rd[0] * rd[0] + rd[1] * rd[1] + rd[2] * rd[2] + 2.0 * (rd[3] * rd[3] + rd[4] * rd[4] + rd[5] * rd[5]);
@@ -380,7 +389,7 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
   __syncthreads();
   lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, -1>(z, tw);
 
-  store_rows_r2c<T, N2, ROWS, NTB>((C2<T>*)d.spec, z, row0, rows_total);
+  store_rows_r2c<T, N2, ROWS, NTB, S>((S*)d.spec, z, row0, rows_total);
   double sums[3] = {acc0, acc1, acc2};
   block_sums<3, NTB>(sums, d.part_f + blockIdx.x, gridDim.x);
 }
@@ -543,7 +552,7 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
 // (C - C0) r_{k+1}, written back over the block's own spectrum rows.
 // Iterates ping-pong between two slots: r_k, x_k sit in slot (k & 1).
 // ---------------------------------------------------------------------------
-template <typename T, int N2, bool ISO, int ROWS = xi_rows<T>(N2), int NTB = NT>
+template <typename T, int N2, bool ISO, int ROWS = xi_rows<T>(N2), int NTB = NT, typename S = C2<T>>
 __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, long rows_total, long nvox) {
   constexpr int RS = N2 + N2 / 16;
   __shared__ C2<T> z[ROWS * 3 * RS];
@@ -552,8 +561,10 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
   if (!d.st->active) return;
   build_twiddles<T, N2, NTB>(tw);
   const long row0 = (long)blockIdx.x * ROWS;
-  C2<T>* spec = (C2<T>*)d.spec;
-  load_rows_c2r<T, N2, ROWS, NTB>(spec, z, row0, rows_total);
+  // binary16 inner solve: eta comes from the FP32 copy, tau goes out in binary16
+  constexpr bool FULL = std::is_same<S, C2<T>>::value;
+  S* spec = (S*)d.spec;
+  load_rows_c2r<T, N2, ROWS, NTB>((const C2<T>*)(FULL ? d.spec : d.spec2), z, row0, rows_total);
   __syncthreads();
   lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, +1>(z, tw);
 
@@ -566,6 +577,7 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
   T* xo = (T*)((it & 1) ? d.x : d.x1);
   T* ro = (T*)((it & 1) ? d.r : d.r1);
   const T* mat = mat_of<T>(d);
+  const T ts = d.h16 ? (T)(d.tau_scale / d.st->dscale) : T(1);   // binary16 spectrum scale
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
   for (int v = threadIdx.x; v < ROWS * N2; v += NTB) {
     const int rr = v / N2, i2 = v % N2;
@@ -608,13 +620,17 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
       acc0 += c0_ip(d.lam0, d.mu0, rd, rd);
       acc1 += (double)frob_w(rn, cr);
       acc2 += rd[0] * rd[0] + rd[1] * rd[1] + rd[2] * rd[2] + 2.0 * (rd[3] * rd[3] + rd[4] * rd[4] + rd[5] * rd[5]);
+      if (d.h16) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) tau[c] *= ts;
+      }
     }
 #pragma unroll
     for (int q = 0; q < 3; ++q) z[(rr * 3 + q) * RS + padx<true>(i2)] = C2<T>{tau[2 * q], tau[2 * q + 1]};
   }
   __syncthreads();
   lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, -1>(z, tw);
-  store_rows_r2c<T, N2, ROWS, NTB>(spec, z, row0, rows_total);
+  store_rows_r2c<T, N2, ROWS, NTB, S>(spec, z, row0, rows_total);
   double sums[3] = {acc0, acc1, acc2};
   block_sums<3, NTB>(sums, d.part_i + blockIdx.x, gridDim.x);
 }
@@ -639,13 +655,18 @@ __global__ __launch_bounds__(NT) void k_bicg_finish(const Desc* __restrict__ des
 // ---------------------------------------------------------------------------
 // ncols is a multiple of 6 (and of V), so a V-group of columns is either all
 // inside or all outside the plane.
-template <typename T, int N1, int CW, int NTB, int DIR, int V>
-__device__ __forceinline__ void ypass_body(C2<T>* base, int ncols, int c0, C2<T>* buf, const C2<T>* tw) {
+// S = H2 (binary16 storage): the forward transform is divided by N1 so that
+// the stored values stay in range.
+template <typename T, int N1, int CW, int NTB, int DIR, int V, typename S>
+__device__ __forceinline__ void ypass_body(S* base, int ncols, int c0, C2<T>* buf, const C2<T>* tw) {
+  constexpr bool FULL = std::is_same<S, C2<T>>::value;
+  static_assert(FULL || V == 1, "binary16 storage moves one value at a time");
   for (int v = threadIdx.x; v < N1 * CW / V; v += NTB) {
     const int i1 = v / (CW / V), col = (v % (CW / V)) * V;
     C2<T> a[V];
     if (c0 + col < ncols) {
-      load_v<T, V>(base + (long)i1 * ncols + col, a);
+      if constexpr (FULL) load_v<T, V>(base + (long)i1 * ncols + col, a);
+      else a[0] = sload<T>(base + (long)i1 * ncols + col);
     } else {
 #pragma unroll
       for (int q = 0; q < V; ++q) a[q] = C2<T>{0, 0};
@@ -659,13 +680,18 @@ __device__ __forceinline__ void ypass_body(C2<T>* base, int ncols, int c0, C2<T>
     if (c0 + col < ncols) {
       C2<T> a[V];
       load_v<T, V>(buf + i1 * CW + col, a);
-      store_v<T, V>(base + (long)i1 * ncols + col, a);
+      if constexpr (FULL) {
+        store_v<T, V>(base + (long)i1 * ncols + col, a);
+      } else {
+        if (DIR < 0) a[0] = a[0] * (T(1) / T(N1));
+        sstore<T>(base + (long)i1 * ncols + col, a[0]);
+      }
     }
   }
 }
 
 template <typename T, int N1, int CW = y_cols<T>(N1), int NTB = y_threads<T>(N1), bool REMAP = true,
-          int V = vec_width<T>()>
+          int V = vec_width<T>(), typename S = C2<T>>
 __global__ __launch_bounds__(NTB) void k_ypass(const Desc* __restrict__ descs, int dir, int ncols, int ntiles) {
   __shared__ __attribute__((aligned(16))) C2<T> buf[N1 * CW];
   __shared__ C2<T> tw[N1];
@@ -675,9 +701,12 @@ __global__ __launch_bounds__(NTB) void k_ypass(const Desc* __restrict__ descs, i
   const int bid = REMAP ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const long i0 = bid / ntiles;
   const int c0 = (bid % ntiles) * CW;
-  C2<T>* base = (C2<T>*)d.spec + i0 * N1 * (long)ncols + c0;
-  if (dir < 0) ypass_body<T, N1, CW, NTB, -1, V>(base, ncols, c0, buf, tw);
-  else ypass_body<T, N1, CW, NTB, +1, V>(base, ncols, c0, buf, tw);
+  // binary16 inner solve (spec2 set only in its descriptors): the inverse
+  // y-transform runs in FP32 on the copy the spectral operator wrote
+  const bool alt = std::is_same<S, C2<T>>::value && d.spec2 != nullptr && dir > 0;
+  S* base = (S*)(alt ? d.spec2 : d.spec) + i0 * N1 * (long)ncols + c0;
+  if (dir < 0) ypass_body<T, N1, CW, NTB, -1, V, S>(base, ncols, c0, buf, tw);
+  else ypass_body<T, N1, CW, NTB, +1, V, S>(base, ncols, c0, buf, tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -751,7 +780,8 @@ __device__ __forceinline__ void spectral_op(int op, T (&in)[6][2], T (&out)[6][2
   }
 }
 
-template <typename T, int N0, int TK = z_cols<T>(N0), int NTB = NT, bool REMAP = true, int V = vec_width<T>()>
+template <typename T, int N0, int TK = z_cols<T>(N0), int NTB = NT, bool REMAP = true, int V = vec_width<T>(),
+          typename S = C2<T>>
 __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, int op, int n1, int h, double scale) {
   constexpr int W = TK * 6;
   __shared__ __attribute__((aligned(16))) C2<T> buf[N0 * W];
@@ -766,12 +796,21 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
   const int bid = REMAP ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int chunk = bid / bpc;
   const long m0 = (long)(bid % bpc) * TK;
-  C2<T>* spec = (C2<T>*)d.spec + (long)chunk * N0 * M * 6;
+  constexpr bool FULL = std::is_same<S, C2<T>>::value;
+  static_assert(FULL || V == 1, "binary16 storage moves one value at a time");
+  S* spec = (S*)d.spec + (long)chunk * N0 * M * 6;
+  // binary16 input; the output (after the spectral operator) goes to the FP32 copy
+  C2<T>* dst = (C2<T>*)(FULL ? d.spec : d.spec2) + (long)chunk * N0 * M * 6;
+  // binary16 storage: the spectral operator also restores the scale of the
+  // forward transforms (the descriptor's factor times the right-hand side's
+  // RMS replaces 1/N)
+  const T sc = FULL ? (T)scale : (T)(d.op_scale * d.st->dscale);
   for (int v = threadIdx.x; v < N0 * W / V; v += NTB) {
     const int i0 = v / (W / V), w = (v % (W / V)) * V;
     C2<T> a[V];
     if (m0 + w / 6 < M) {
-      load_v<T, V>(spec + ((long)i0 * M + m0) * 6 + w, a);
+      if constexpr (FULL) load_v<T, V>(spec + ((long)i0 * M + m0) * 6 + w, a);
+      else a[0] = sload<T>(spec + ((long)i0 * M + m0) * 6 + w);
     } else {
 #pragma unroll
       for (int q = 0; q < V; ++q) a[q] = C2<T>{0, 0};
@@ -804,7 +843,7 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
 #pragma unroll
       for (int c = 0; c < 6; ++c) out[c][0] = out[c][1] = T(0);
     } else {
-      spectral_op<T>(op, in, out, (T)k0s, (T)k1s, (T)k2, d.lam0, d.mu0, (T)scale);
+      spectral_op<T>(op, in, out, (T)k0s, (T)k1s, (T)k2, d.lam0, d.mu0, sc);
     }
 #pragma unroll
     for (int c = 0; c < 6; c += V) {
@@ -821,7 +860,7 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
     if (m0 + w / 6 < M) {
       C2<T> a[V];
       load_v<T, V>(buf + i0 * W + w, a);
-      store_v<T, V>(spec + ((long)i0 * M + m0) * 6 + w, a);
+      store_v<T, V>(dst + ((long)i0 * M + m0) * 6 + w, a);
     }
   }
 }

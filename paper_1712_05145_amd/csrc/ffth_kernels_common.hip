@@ -210,6 +210,7 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
       st->proj++;
       in->active = si[0] > 0.0 ? 1 : 0;
       in->nb2 = si[0];
+      in->dscale = si[0] > 0.0 ? sqrt(si[0] * d.inv_nvox) : 1.0;
       in->rr = si[1];
       in->first = 1;
       in->iters = 0;
@@ -250,6 +251,7 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
       } else {
         in->active = 1;
         in->nb2 = si[0];
+        in->dscale = si[0] > 0.0 ? sqrt(si[0] * d.inv_nvox) : 1.0;
         in->rr = si[1];
         in->first = 1;
         in->iters = 0;

@@ -23,16 +23,19 @@ template <typename T> struct Launch {
   static int xi_rows(int n, int v);
   static int y_cols(int n, int v);
   static int z_cols(int n, int v);
-  static hipError_t xfwd(int n2, bool iso, int v, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows,
-                         long nvox);
+  // h16: spectrum stored as binary16 (FP32 only; the mixed scheme's inner solve)
+  static hipError_t xfwd(int n2, bool iso, int v, bool h16, dim3 grid, hipStream_t s, const Desc* d, int mode,
+                         long rows, long nvox);
   static hipError_t xinv(int n2, bool iso, int v, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows,
                          long nvox);
   // fused three-term CG iteration (x-inverse, update, x-forward); x-inverse tiles
-  static hipError_t xcg3(int n2, bool iso, int v, dim3 grid, hipStream_t s, const Desc* d, long rows, long nvox);
+  static hipError_t xcg3(int n2, bool iso, int v, bool h16, dim3 grid, hipStream_t s, const Desc* d, long rows,
+                         long nvox);
   // BiCGSTAB: the pending x update of loads that stopped (n = 6 * voxels)
   static hipError_t bicg_finish(dim3 grid, hipStream_t s, const Desc* d, long n);
-  static hipError_t ypass(int n1, int v, dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols, int ntiles);
-  static hipError_t zpass(int n0, int v, dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h,
+  static hipError_t ypass(int n1, int v, bool h16, dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols,
+                          int ntiles);
+  static hipError_t zpass(int n0, int v, bool h16, dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h,
                           double scale);
 };
 

@@ -25,6 +25,7 @@ struct SolverState {
   int32_t fp64_apps; // FP64 operator applications (outer state only)
   int32_t proj;      // FP32 projection passes (outer state only)
   double omega;      // BiCGSTAB: omega of the last iteration
+  double dscale;     // inner state: RMS of the inner right-hand side (binary16 spectrum scale)
   int32_t pending;   // BiCGSTAB: x += alpha p + omega s of the last iteration not applied yet
   int32_t pad;
 };
@@ -53,6 +54,7 @@ struct Desc {
   void* io;                // generic input field (copy-in mode; order-1 p_2 output)
   void* out;               // generic output field (store / accumulate modes)
   void* spec;              // half spectrum [n0][n1][n2/2][6] complex
+  void* spec2;             // binary16 inner solve: FP32 copy after the spectral operator
   double* part_f;          // [nblk][8] block sums of the forward x-pass
   double* part_i;          // [nblk][8] block sums of the inverse x-pass / pointwise kernels
   SolverState* st;         // gating state
@@ -61,9 +63,13 @@ struct Desc {
   double E[6];             // macroscopic strain, tensor components
   double G[18];            // order-1 gradient load G[J*3 + j]
   double H[54];            // order-2 load H[J*9 + j*3 + m] = d^2 E_J / dY_j dY_m
+  double inv_nvox;         // 1 / voxels
+  double tau_scale;        // binary16 spectrum: factor on the polarization before the x-transform
+  double op_scale;         // binary16 spectrum: factor of the spectral operator (replaces 1/N)
   int32_t nc;              // components of io (3 or 6)
   int32_t r_f32;           // residual stored as FP32
-  int32_t pad[2];
+  int32_t h16;             // the inner solve keeps its spectrum in binary16
+  int32_t pad;
 };
 
 // x-pass (forward) modes

@@ -41,7 +41,7 @@ class ffth_problem(ctypes.Structure):
 class ffth_opts(ctypes.Structure):
     _fields_ = [("scheme", ctypes.c_int32), ("precision", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("inner_tol", ctypes.c_double), ("max_outer", ctypes.c_int32),
-                ("check_every", ctypes.c_int32), ("autotune", ctypes.c_int32)]
+                ("check_every", ctypes.c_int32), ("autotune", ctypes.c_int32), ("spectrum16", ctypes.c_int32)]
 
 
 class ffth_result(ctypes.Structure):
@@ -64,6 +64,8 @@ _lib = None
 SIGNATURES = [
     ("ffth_default_opts", None, [ctypes.POINTER(ffth_opts)]),
     ("ffth_size_supported", ctypes.c_int32, [ctypes.c_int32]),
+    ("ffth_stiffness_contrast", ctypes.c_double,
+     [ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     ("ffth_workspace_bytes", ctypes.c_size_t,
      [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ffth_opts)]),
     ("ffth_plan_create", ctypes.c_int,
@@ -144,7 +146,7 @@ def _darr(a):
 
 
 def make_opts(scheme="cg", precision="mixed", tol=1e-8, max_iter=20000, inner_tol=1e-2, max_outer=30,
-              check_every=8, autotune=True):
+              check_every=8, autotune=True, spectrum16=True):
     o = ffth_opts()
     load().ffth_default_opts(ctypes.byref(o))
     o.scheme = SCHEMES[scheme] if isinstance(scheme, str) else scheme
@@ -152,6 +154,7 @@ def make_opts(scheme="cg", precision="mixed", tol=1e-8, max_iter=20000, inner_to
     o.tol, o.max_iter, o.inner_tol = tol, max_iter, inner_tol
     o.max_outer, o.check_every = max_outer, check_every
     o.autotune = 1 if autotune else 0
+    o.spectrum16 = 1 if spectrum16 else 0
     return o
 
 
@@ -168,6 +171,20 @@ def ffth_set_tile_variants(plan, variants):
 
 def ffth_size_supported(n):
     return bool(load().ffth_size_supported(int(n)))
+
+
+SPECTRUM16_MAX_CONTRAST = 400.0   # FFTH_SPECTRUM16_MAX_CONTRAST
+SPECTRUM16_MIN_VOXELS = 128 ** 3   # FFTH_SPECTRUM16_MIN_VOXELS
+
+
+def ffth_stiffness_contrast(lame=None, voigt21=None):
+    """Largest over smallest eigen-modulus (Mandel form) across the phases;
+    inf when a phase is not positive definite."""
+    if lame is not None:
+        a, ptr = _darr(np.asarray(lame, dtype=np.float64).reshape(-1, 2))
+        return float(load().ffth_stiffness_contrast(a.shape[0], ptr, None))
+    a, ptr = _darr(np.asarray(voigt21, dtype=np.float64).reshape(-1, 21))
+    return float(load().ffth_stiffness_contrast(a.shape[0], None, ptr))
 
 
 def ffth_workspace_bytes(n, nphases, nloads, order, opts):
@@ -260,7 +277,7 @@ class Solver:
 
     def __init__(self, phase, lam0, mu0, lame=None, voigt21=None, nloads=1, order=0, scheme="cg",
                  precision="mixed", tol=1e-8, max_iter=20000, inner_tol=1e-2, max_outer=30, check_every=8,
-                 autotune=True, device="cuda:0", stream=None):
+                 autotune=True, spectrum16=True, device="cuda:0", stream=None):
         import torch
         self.torch = torch
         self.device = torch.device(device)
@@ -273,7 +290,8 @@ class Solver:
         self.nvox = int(np.prod(self.n))
         self.nloads = nloads
         self.order = order
-        self.opts = make_opts(scheme, precision, tol, max_iter, inner_tol, max_outer, check_every, autotune)
+        self.opts = make_opts(scheme, precision, tol, max_iter, inner_tol, max_outer, check_every, autotune,
+                              spectrum16)
         self._lame = None if lame is None else _darr(lame)
         self._v21 = None if voigt21 is None else _darr(voigt21)
         nph = (len(np.asarray(lame).reshape(-1, 2)) if lame is not None

@@ -14,7 +14,7 @@ int main(void) {
   F(ffth_problem, stiffness); F(ffth_problem, lambda0); F(ffth_problem, mu0);
   Z(ffth_opts);
   F(ffth_opts, scheme); F(ffth_opts, precision); F(ffth_opts, tol); F(ffth_opts, max_iter);
-  F(ffth_opts, inner_tol); F(ffth_opts, max_outer); F(ffth_opts, check_every); F(ffth_opts, autotune);
+  F(ffth_opts, inner_tol); F(ffth_opts, max_outer); F(ffth_opts, check_every); F(ffth_opts, autotune); F(ffth_opts, spectrum16);
   Z(ffth_result);
   F(ffth_result, status); F(ffth_result, iters); F(ffth_result, outer_iters); F(ffth_result, fp64_applications);
   F(ffth_result, projections); F(ffth_result, residual); F(ffth_result, mean_stress); F(ffth_result, g_mean);

@@ -96,3 +96,51 @@ def test_small_workspace_and_misaligned_rejected():
                                 ctypes.c_void_p(4100), 1 << 30, None) == ffth.FFTH_ERR_INVALID
     assert lib.ffth_plan_destroy(None) == ffth.FFTH_ERR_INVALID
     assert lib.ffth_status_string(3).decode() == "not converged"
+
+
+def _mandel(v21):
+    c = np.zeros((6, 6))
+    c[np.triu_indices(6)] = v21
+    c = c + np.triu(c, 1).T
+    w = np.array([1, 1, 1, np.sqrt(2), np.sqrt(2), np.sqrt(2)])
+    return c * np.outer(w, w)
+
+
+def test_stiffness_contrast_matches_eigenvalues():
+    """Host-only: the contrast that gates the binary16 spectrum equals
+    max / min of numpy's eigenvalues of the Mandel stiffness over the phases."""
+    rng = np.random.default_rng(5)
+    lame = np.array([[1.0, 0.5], [30.0, 12.0], [2.0, 7.0]])
+    ev = np.concatenate([[3 * l + 2 * m] + [2 * m] * 5 for l, m in lame])
+    assert abs(ffth.ffth_stiffness_contrast(lame=lame) - ev.max() / ev.min()) < 1e-12 * ev.max() / ev.min()
+    v = []
+    for _ in range(4):                       # generic anisotropic SPD phases
+        a = rng.standard_normal((6, 6))
+        m = a @ a.T + 0.5 * np.eye(6)        # Mandel matrix
+        w = np.array([1, 1, 1, np.sqrt(2), np.sqrt(2), np.sqrt(2)])
+        v.append((m / np.outer(w, w))[np.triu_indices(6)])
+    v = np.array(v)
+    ev = np.concatenate([np.linalg.eigvalsh(_mandel(x)) for x in v])
+    got = ffth.ffth_stiffness_contrast(voigt21=v)
+    assert abs(got - ev.max() / ev.min()) < 1e-9 * ev.max() / ev.min()
+    # the isotropic table written as Voigt gives the same contrast
+    iso21 = []
+    for l, m in lame:
+        c = np.zeros((6, 6))
+        c[:3, :3] = l
+        c[np.arange(3), np.arange(3)] += 2 * m
+        c[np.arange(3, 6), np.arange(3, 6)] = m
+        iso21.append(c[np.triu_indices(6)])
+    assert abs(ffth.ffth_stiffness_contrast(voigt21=np.array(iso21)) - ffth.ffth_stiffness_contrast(lame=lame)) \
+        < 1e-9 * ffth.ffth_stiffness_contrast(lame=lame)
+    assert ffth.ffth_stiffness_contrast(lame=[[1.0, -0.1]]) == np.inf          # not positive definite
+    lib = ffth.load()
+    assert np.isnan(lib.ffth_stiffness_contrast(0, None, None))
+
+
+def test_spectrum16_limit_matches_header():
+    txt = open(os.path.join(ROOT, "include", "ffth.h")).read()
+    m = re.search(r"#define FFTH_SPECTRUM16_MAX_CONTRAST ([0-9.eE+-]+)", txt)
+    assert m and float(m.group(1)) == ffth.SPECTRUM16_MAX_CONTRAST
+    m = re.search(r"#define FFTH_SPECTRUM16_MIN_VOXELS ([0-9]+)", txt)
+    assert m and int(m.group(1)) == ffth.SPECTRUM16_MIN_VOXELS

@@ -381,6 +381,40 @@ def test_mixed_three_term_inner_iterations_track_fp64_cg():
     assert its["mixed"] <= 1.3 * its["fp64"] + 12
 
 
+def test_spectrum16_agrees_with_fp32_spectrum_and_is_gated():
+    """Binary16 forward spectrum in the inner solve (128^3): same effective
+    stiffness to the solve's accuracy and about the same iterations as the FP32
+    spectrum when the stiffness contrast is within the limit; above it, and on
+    grids below the size limit, the plan keeps FP32, so switching the option
+    changes nothing (bit-identical results)."""
+    torch = require_gpu()
+    low = M.random_spheres(128, 6, seed=3)                    # Young 1 / 100: contrast 325
+    high = M.overlapping_spheres(128, 0.25, 500.0, 7)         # contrast 1625
+    small = M.random_spheres(64, 6, seed=3)
+    assert ffth.ffth_stiffness_contrast(lame=low[1]) <= ffth.SPECTRUM16_MAX_CONTRAST
+    assert ffth.ffth_stiffness_contrast(lame=high[1]) > ffth.SPECTRUM16_MAX_CONTRAST
+    assert low[0].size >= ffth.SPECTRUM16_MIN_VOXELS > small[0].size
+    for name, (phase, lame) in (("low", low), ("high", high), ("small", small)):
+        print("case spectrum16", name, flush=True)
+        lam0, mu0 = M.midpoint_reference(lame)
+        out, its = {}, {}
+        for h16 in (True, False):
+            s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, precision="mixed", tol=1e-9, spectrum16=h16)
+            _, res = s.solve_order0(np.eye(6))
+            s.close()
+            assert all(r["status"] == 0 and r["residual"] < 1e-9 for r in res)
+            out[h16] = np.array([r["mean_stress"] for r in res]).T
+            its[h16] = sum(r["iters"] for r in res)
+        print("iterations", name, its, flush=True)
+        if name == "low":
+            d = np.sqrt(np.outer(np.diag(out[False]), np.diag(out[False])))
+            assert np.all(np.abs(out[True] - out[False]) <= 1e-8 * d)
+            assert its[True] <= 1.1 * its[False] + 8
+            assert not np.array_equal(out[True], out[False])      # the binary16 path did run
+        else:
+            assert its[True] == its[False] and np.array_equal(out[True], out[False])
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_bicgstab_order0_parity_sphere16(sphere16_oracle, precision):
     """BiCGSTAB (the paper's solver) on the six unit loads in one batched call."""

@@ -32,11 +32,17 @@ def _drain(srv, ids):
 
 
 def test_alone_equals_mix_and_plan_path():
+    """Request a (128^3, stiffness contrast within the binary16 limit) shares its
+    grid with a request above the limit: the server runs the two in separate
+    launch groups, and a's results are the same alone, in the mix and through
+    the plan path."""
     torch = require_gpu()
     from paper_1712_05145_amd.serving import Server
-    a = _req(32, 0.25, 50.0, 1)
-    others = [_req(64, 0.3, 200.0, 2), _req(48, 0.2, 10.0, 3), _req(32, 0.35, 400.0, 4), _req(64, 0.1, 5.0, 5)]
-    budget = 2 << 30
+    a = _req(128, 0.25, 50.0, 1)
+    others = [_req(64, 0.3, 200.0, 2), _req(48, 0.2, 10.0, 3), _req(128, 0.35, 400.0, 4), _req(64, 0.1, 5.0, 5)]
+    lim = ffth.SPECTRUM16_MAX_CONTRAST
+    assert ffth.ffth_stiffness_contrast(lame=a[1]) <= lim < ffth.ffth_stiffness_contrast(lame=others[2][1])
+    budget = 16 << 30
     s1 = Server(budget, max_running=8)
     ida = s1.submit(*a, np.eye(6))
     alone = _drain(s1, [ida])[ida]

@@ -211,6 +211,22 @@ template <typename T, int V> __device__ __forceinline__ void store_v(C2<T>* p, c
   }
 }
 
+// G adjacent binary16 complex values moved with one access of 4 G bytes
+// (p aligned to that size).
+template <int G> struct alignas(4 * G) H2G { H2 h[G]; };
+template <typename T, int G> __device__ __forceinline__ void hload_g(const H2* p, C2<T> (&o)[G]) {
+  const H2G<G> q = *reinterpret_cast<const H2G<G>*>(p);
+#pragma unroll
+  for (int i = 0; i < G; ++i) o[i] = C2<T>{(T)q.h[i].x, (T)q.h[i].y};
+}
+template <typename T, int G> __device__ __forceinline__ void hstore_g(H2* p, const C2<T> (&o)[G]) {
+  H2G<G> q;
+#pragma unroll
+  for (int i = 0; i < G; ++i) q.h[i] = H2{(_Float16)o[i].x, (_Float16)o[i].y};
+  *reinterpret_cast<H2G<G>*>(p) = q;
+}
+
+
 // One Stockham stage.  Work items are (group of V adjacent sequences, butterfly).
 // V = 2 requires FFAST layouts with sequence stride FS = 1 (adjacent sequences).
 template <typename T, int N, int S, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR, int V>

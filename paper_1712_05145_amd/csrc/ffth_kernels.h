@@ -653,40 +653,84 @@ __global__ __launch_bounds__(NT) void k_bicg_finish(const Desc* __restrict__ des
 // y-pass: complex FFT along axis 1, in place.  Block = one i0 plane, CW
 // consecutive columns of the [n1][n2/2 * 6] plane.
 // ---------------------------------------------------------------------------
-// ncols is a multiple of 6 (and of V), so a V-group of columns is either all
-// inside or all outside the plane.
+// ncols is a multiple of 6, so an access group of 2 columns is either all
+// inside or all outside the plane (groups of 4 are used only when ncols is a
+// multiple of 4).
 // S = H2 (binary16 storage): the forward transform is divided by N1 so that
 // the stored values stay in range.
+// Binary16 tile transfers, G columns per access (ncols and c0 multiples of G,
+// so a group is either all inside or all outside the plane).
+template <typename T, int N1, int CW, int NTB, int G>
+__device__ __forceinline__ void y_h2_load(const H2* base, int ncols, int c0, C2<T>* buf) {
+  for (int v = threadIdx.x; v < N1 * CW / G; v += NTB) {
+    const int i1 = v / (CW / G), col = (v % (CW / G)) * G;
+    C2<T> a[G];
+    if (c0 + col < ncols) {
+      hload_g<T, G>(base + (long)i1 * ncols + col, a);
+    } else {
+#pragma unroll
+      for (int q = 0; q < G; ++q) a[q] = C2<T>{0, 0};
+    }
+#pragma unroll
+    for (int q = 0; q < G; ++q) buf[i1 * CW + col + q] = a[q];
+  }
+}
+template <typename T, int N1, int CW, int NTB, int G>
+__device__ __forceinline__ void y_h2_store(H2* base, int ncols, int c0, const C2<T>* buf, T scale) {
+  for (int v = threadIdx.x; v < N1 * CW / G; v += NTB) {
+    const int i1 = v / (CW / G), col = (v % (CW / G)) * G;
+    if (c0 + col < ncols) {
+      C2<T> a[G];
+#pragma unroll
+      for (int q = 0; q < G; ++q) a[q] = buf[i1 * CW + col + q] * scale;
+      hstore_g<T, G>(base + (long)i1 * ncols + col, a);
+    }
+  }
+}
+
 template <typename T, int N1, int CW, int NTB, int DIR, int V, typename S>
 __device__ __forceinline__ void ypass_body(S* base, int ncols, int c0, C2<T>* buf, const C2<T>* tw) {
   constexpr bool FULL = std::is_same<S, C2<T>>::value;
-  static_assert(FULL || V == 1, "binary16 storage moves one value at a time");
-  for (int v = threadIdx.x; v < N1 * CW / V; v += NTB) {
-    const int i1 = v / (CW / V), col = (v % (CW / V)) * V;
-    C2<T> a[V];
-    if (c0 + col < ncols) {
-      if constexpr (FULL) load_v<T, V>(base + (long)i1 * ncols + col, a);
-      else a[0] = sload<T>(base + (long)i1 * ncols + col);
-    } else {
+  static_assert(FULL || V == 1, "binary16 storage keeps one sequence per LDS slot");
+  // binary16: up to 4 columns (16 bytes) per access when the plane width allows
+  constexpr int G = CW % 4 == 0 ? 4 : CW % 2 == 0 ? 2 : 1;
+  const bool wide = ncols % G == 0;
+  // FP32: two columns (16 bytes) per access (ncols = 6 kc is even)
+  constexpr int GF = (sizeof(T) == 4 && CW % 2 == 0) ? 2 : 1;
+  if constexpr (FULL) {
+    for (int v = threadIdx.x; v < N1 * CW / GF; v += NTB) {
+      const int i1 = v / (CW / GF), col = (v % (CW / GF)) * GF;
+      C2<T> a[GF];
+      if (c0 + col < ncols) {
+        load_v<T, GF>(base + (long)i1 * ncols + col, a);
+      } else {
 #pragma unroll
-      for (int q = 0; q < V; ++q) a[q] = C2<T>{0, 0};
+        for (int q = 0; q < GF; ++q) a[q] = C2<T>{0, 0};
+      }
+#pragma unroll
+      for (int q = 0; q < GF; ++q) buf[i1 * CW + col + q] = a[q];
     }
-    store_v<T, V>(buf + i1 * CW + col, a);
+  } else {
+    if (wide) y_h2_load<T, N1, CW, NTB, G>(base, ncols, c0, buf);
+    else y_h2_load<T, N1, CW, NTB, 1>(base, ncols, c0, buf);
   }
   __syncthreads();
   lds_fft<T, N1, CW, NTB, CW, 1, true, false, DIR, V>(buf, tw);
-  for (int v = threadIdx.x; v < N1 * CW / V; v += NTB) {
-    const int i1 = v / (CW / V), col = (v % (CW / V)) * V;
-    if (c0 + col < ncols) {
-      C2<T> a[V];
-      load_v<T, V>(buf + i1 * CW + col, a);
-      if constexpr (FULL) {
-        store_v<T, V>(base + (long)i1 * ncols + col, a);
-      } else {
-        if (DIR < 0) a[0] = a[0] * (T(1) / T(N1));
-        sstore<T>(base + (long)i1 * ncols + col, a[0]);
+  if constexpr (FULL) {
+    for (int v = threadIdx.x; v < N1 * CW / GF; v += NTB) {
+      const int i1 = v / (CW / GF), col = (v % (CW / GF)) * GF;
+      if (c0 + col < ncols) {
+        C2<T> a[GF];
+#pragma unroll
+        for (int q = 0; q < GF; ++q) a[q] = buf[i1 * CW + col + q];
+        store_v<T, GF>(base + (long)i1 * ncols + col, a);
       }
     }
+  } else {
+    // the forward transform is divided by N1 so that the stored values stay in range
+    const T sc = DIR < 0 ? T(1) / T(N1) : T(1);
+    if (wide) y_h2_store<T, N1, CW, NTB, G>(base, ncols, c0, buf, sc);
+    else y_h2_store<T, N1, CW, NTB, 1>(base, ncols, c0, buf, sc);
   }
 }
 
@@ -797,7 +841,10 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
   const int chunk = bid / bpc;
   const long m0 = (long)(bid % bpc) * TK;
   constexpr bool FULL = std::is_same<S, C2<T>>::value;
-  static_assert(FULL || V == 1, "binary16 storage moves one value at a time");
+  // global accesses move GZ adjacent components (16 bytes in FP32, 8 in
+  // binary16); W is even and so is every column's offset, so a group never
+  // straddles a column
+  constexpr int GZ = sizeof(T) == 4 ? 2 : 1;
   S* spec = (S*)d.spec + (long)chunk * N0 * M * 6;
   // binary16 input; the output (after the spectral operator) goes to the FP32 copy
   C2<T>* dst = (C2<T>*)(FULL ? d.spec : d.spec2) + (long)chunk * N0 * M * 6;
@@ -805,17 +852,18 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
   // forward transforms (the descriptor's factor times the right-hand side's
   // RMS replaces 1/N)
   const T sc = FULL ? (T)scale : (T)(d.op_scale * d.st->dscale);
-  for (int v = threadIdx.x; v < N0 * W / V; v += NTB) {
-    const int i0 = v / (W / V), w = (v % (W / V)) * V;
-    C2<T> a[V];
+  for (int v = threadIdx.x; v < N0 * W / GZ; v += NTB) {
+    const int i0 = v / (W / GZ), w = (v % (W / GZ)) * GZ;
+    C2<T> a[GZ];
     if (m0 + w / 6 < M) {
-      if constexpr (FULL) load_v<T, V>(spec + ((long)i0 * M + m0) * 6 + w, a);
-      else a[0] = sload<T>(spec + ((long)i0 * M + m0) * 6 + w);
+      if constexpr (FULL) load_v<T, GZ>(spec + ((long)i0 * M + m0) * 6 + w, a);
+      else hload_g<T, GZ>(spec + ((long)i0 * M + m0) * 6 + w, a);
     } else {
 #pragma unroll
-      for (int q = 0; q < V; ++q) a[q] = C2<T>{0, 0};
+      for (int q = 0; q < GZ; ++q) a[q] = C2<T>{0, 0};
     }
-    store_v<T, V>(buf + i0 * W + w, a);
+#pragma unroll
+    for (int q = 0; q < GZ; ++q) buf[i0 * W + w + q] = a[q];
   }
   __syncthreads();
   if constexpr (N0 > 1) lds_fft<T, N0, W, NTB, W, 1, true, false, -1, V>(buf, tw);
@@ -855,12 +903,13 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
   }
   __syncthreads();
   if constexpr (N0 > 1) lds_fft<T, N0, W, NTB, W, 1, true, false, +1, V>(buf, tw);
-  for (int v = threadIdx.x; v < N0 * W / V; v += NTB) {
-    const int i0 = v / (W / V), w = (v % (W / V)) * V;
+  for (int v = threadIdx.x; v < N0 * W / GZ; v += NTB) {
+    const int i0 = v / (W / GZ), w = (v % (W / GZ)) * GZ;
     if (m0 + w / 6 < M) {
-      C2<T> a[V];
-      load_v<T, V>(buf + i0 * W + w, a);
-      store_v<T, V>(dst + ((long)i0 * M + m0) * 6 + w, a);
+      C2<T> a[GZ];
+#pragma unroll
+      for (int q = 0; q < GZ; ++q) a[q] = buf[i0 * W + w + q];
+      store_v<T, GZ>(dst + ((long)i0 * M + m0) * 6 + w, a);
     }
   }
 }

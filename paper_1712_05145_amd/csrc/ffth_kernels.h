@@ -59,8 +59,9 @@ template <typename T> constexpr int z_cols(int n) {
 // default above, 1 and 2 halve / double the tile (or swap the block size of
 // the y-pass), within 96 KB of LDS per block; 3 keeps the x tile of 0 with one
 // wave per block (lengths whose Stockham stages have fewer butterflies than
-// the default block has threads) and gives the z-pass three times the columns
-// with 512 threads (rows of >= 144 contiguous bytes).
+// the default block has threads).  The z-pass takes twice the columns (1),
+// four times with 512 threads (2) or three times with 512 threads (3): rows
+// of >= 144 contiguous bytes in FP32.
 template <typename T> constexpr int lds_cap_rows(int n) {          // x-pass rows within 96 KB
   int r = 98304 / (3 * (n + n / 16) * (int)(2 * sizeof(T)));
   return r < 1 ? 1 : pow2_floor(r);
@@ -78,13 +79,13 @@ template <typename T> constexpr int y_cols_v(int n, int v) {
   return c;
 }
 template <typename T> constexpr int x_threads_v(int, int v) { return v == 3 ? 64 : NT; }
-template <typename T> constexpr int z_threads_v(int, int v) { return v == 3 ? 512 : NT; }
+template <typename T> constexpr int z_threads_v(int, int v) { return v >= 2 ? 512 : NT; }
 template <typename T> constexpr int y_threads_v(int n, int v) {
   return v == 1 ? (y_threads<T>(n) == 512 ? 256 : 512) : v == 2 ? 256 : y_threads<T>(n);
 }
 template <typename T> constexpr int z_cols_v(int n, int v) {
   int c = z_cols<T>(n);
-  c = v == 1 ? 2 * c : v == 2 ? (c > 1 ? c / 2 : 1) : v == 3 ? 3 * c : c;
+  c = v == 1 ? 2 * c : v == 2 ? 4 * c : v == 3 ? 3 * c : c;
   const int cap = 98304 / (n * 6 * (int)(2 * sizeof(T)));
   c = c > cap ? (cap < 1 ? 1 : pow2_floor(cap)) : c;
   return c;
@@ -852,18 +853,32 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
   // forward transforms (the descriptor's factor times the right-hand side's
   // RMS replaces 1/N)
   const T sc = FULL ? (T)scale : (T)(d.op_scale * d.st->dscale);
-  for (int v = threadIdx.x; v < N0 * W / GZ; v += NTB) {
-    const int i0 = v / (W / GZ), w = (v % (W / GZ)) * GZ;
-    C2<T> a[GZ];
-    if (m0 + w / 6 < M) {
-      if constexpr (FULL) load_v<T, GZ>(spec + ((long)i0 * M + m0) * 6 + w, a);
-      else hload_g<T, GZ>(spec + ((long)i0 * M + m0) * 6 + w, a);
-    } else {
+  // all of a thread's loads are issued before the first LDS write, so their
+  // latencies overlap (the tile's rows are far apart in memory)
+  constexpr int NA = N0 * W / GZ, NL = (NA + NTB - 1) / NTB;
+  {
+    C2<T> a[NL][GZ];
 #pragma unroll
-      for (int q = 0; q < GZ; ++q) a[q] = C2<T>{0, 0};
+    for (int k = 0; k < NL; ++k) {
+      const int v = threadIdx.x + k * NTB;
+      const int i0 = v / (W / GZ), w = (v % (W / GZ)) * GZ;
+      if ((NA % NTB == 0 || v < NA) && m0 + w / 6 < M) {
+        if constexpr (FULL) load_v<T, GZ>(spec + ((long)i0 * M + m0) * 6 + w, a[k]);
+        else hload_g<T, GZ>(spec + ((long)i0 * M + m0) * 6 + w, a[k]);
+      } else {
+#pragma unroll
+        for (int q = 0; q < GZ; ++q) a[k][q] = C2<T>{0, 0};
+      }
     }
 #pragma unroll
-    for (int q = 0; q < GZ; ++q) buf[i0 * W + w + q] = a[q];
+    for (int k = 0; k < NL; ++k) {
+      const int v = threadIdx.x + k * NTB;
+      const int i0 = v / (W / GZ), w = (v % (W / GZ)) * GZ;
+      if (NA % NTB == 0 || v < NA) {
+#pragma unroll
+        for (int q = 0; q < GZ; ++q) buf[i0 * W + w + q] = a[k][q];
+      }
+    }
   }
   __syncthreads();
   if constexpr (N0 > 1) lds_fft<T, N0, W, NTB, W, 1, true, false, -1, V>(buf, tw);

@@ -286,7 +286,8 @@ def main():
             entry["alg_bytes_per_voxel_per_load"] = round(alg_bytes(c, u) / (nvox * u), 2)
             entry["achieved_GBs"] = round(alg_bytes(c, u) / (ms * 1e-3) / 1e9, 1)
         kernels[c] = entry
-    t_unit = measured_traffic(cat)
+    # the committed counters were taken with the binary16 forward spectrum
+    t_unit = None if args.no_spectrum16 else measured_traffic(cat)
     upl = units / max(launches, 1)
     roofline = {"bound": "hbm", "kernel": cat, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

@@ -108,8 +108,10 @@ typedef struct {
                                  after the operator), on grids of at least
                                  FFTH_SPECTRUM16_MIN_VOXELS voxels whose stiffness
                                  contrast (ffth_stiffness_contrast) is at most
-                                 FFTH_SPECTRUM16_MAX_CONTRAST; 0: FP32 throughout.
-                                 The FP64 defect correction sets the final accuracy    */
+                                 FFTH_SPECTRUM16_MAX_CONTRAST; 2: binary16 on every
+                                 grid and contrast (more inner iterations at high
+                                 contrast); 0: FP32 throughout.  The FP64 defect
+                                 correction sets the final accuracy                    */
 } ffth_opts;
 
 typedef struct {

@@ -111,6 +111,7 @@ bool opts_valid(const ffth_opts& o) {
   if (o.precision < FFTH_FP64 || o.precision > FFTH_MIXED) return false;
   if (!(o.tol > 0.0) || o.max_iter < 1 || o.check_every < 1) return false;
   if (o.precision == FFTH_MIXED && (!(o.inner_tol > 0.0) || o.inner_tol >= 1.0 || o.max_outer < 1)) return false;
+  if (o.spectrum16 < 0 || o.spectrum16 > 2) return false;
   return true;
 }
 
@@ -1245,8 +1246,9 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
   // above FFTH_SPECTRUM16_MAX_CONTRAST it would cost iterations, so FP32 is
   // kept; below FFTH_SPECTRUM16_MIN_VOXELS the launches are latency-bound
   P->contrast = stiffness_contrast(p->nphases, P->iso, p->lame, p->stiffness);
-  P->h16 = o->precision == FFTH_MIXED && o->scheme == FFTH_CG && o->spectrum16 != 0 &&
-           P->contrast <= FFTH_SPECTRUM16_MAX_CONTRAST && P->nvox >= FFTH_SPECTRUM16_MIN_VOXELS;
+  P->h16 = o->precision == FFTH_MIXED && o->scheme == FFTH_CG &&
+           (o->spectrum16 == 2 || (o->spectrum16 == 1 && P->contrast <= FFTH_SPECTRUM16_MAX_CONTRAST &&
+                                   P->nvox >= FFTH_SPECTRUM16_MIN_VOXELS));
   bool ok = hip_ok(hipMemcpyAsync(P->mat64, m64.data(), m64.size() * 8, hipMemcpyHostToDevice, P->stream), "copy") &&
             hip_ok(hipMemcpyAsync(P->mat32, m32.data(), m32.size() * 4, hipMemcpyHostToDevice, P->stream), "copy");
   // phase ids must index the table

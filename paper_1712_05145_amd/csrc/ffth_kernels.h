@@ -146,6 +146,12 @@ template <typename T> __device__ __forceinline__ double frob_d(const T (&a)[6], 
   for (int c = 0; c < 6; ++c) s += (c < 3 ? 1.0 : 2.0) * (double)a[c] * (double)b[c];
   return s;
 }
+// a : b for a block sum: FP32 operands are multiplied in FP64 (products of
+// small residuals would underflow in FP32); FP64 keeps frob_w's order
+template <typename T> __device__ __forceinline__ double frob_acc(const T (&a)[6], const T (&b)[6]) {
+  if constexpr (sizeof(T) == 4) return frob_d(a, b);
+  else return frob_w(a, b);
+}
 // C0 inner product density lam0 tr a tr b + 2 mu0 a:b
 __device__ __forceinline__ double c0_ip(double lam0, double mu0, const double (&a)[6], const double (&b)[6]) {
   const double ta = a[0] + a[1] + a[2], tb = b[0] + b[1] + b[2];
@@ -278,7 +284,7 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
         apply_mat<T, ISO>(mat, ph, true, x, dx);
 #pragma unroll
         for (int c = 0; c < 6; ++c) tau[c] = pr[c] + dx[c];
-        acc0 += (double)frob_w(pr, pr);
+        acc0 += frob_acc(pr, pr);
       } else if (mode == XF_MATVEC) {
         const T* vp = (const T*)d.x;
         T x[6];
@@ -298,7 +304,7 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
         apply_mat<T, ISO>(mat, ph, true, p, tau);
         T cp[6];
         apply_mat<T, ISO>(mat, ph, false, p, cp);
-        acc0 += (double)frob_w(p, cp);
+        acc0 += frob_acc(p, cp);
       } else if (mode == XF_R3) {
         // start of the three-term CG: tau = (C - C0) r_0 and the sums
         // <r, r>_C0, <r, C r> (= <r, A r>_C0 on compatible r) and ||r||^2
@@ -319,7 +325,7 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
           for (int c = 0; c < 6; ++c) tau[c] *= ts;
         }
         acc0 += c0_ip(d.lam0, d.mu0, rd, rd);
-        acc1 += (double)frob_w(r, cr);
+        acc1 += frob_acc(r, cr);
         acc2 += rd[0] * rd[0] + rd[1] * rd[1] + rd[2] * rd[2] + 2.0 * (rd[3] * rd[3] + rd[4] * rd[4] + rd[5] * rd[5]);
       } else if (mode == XF_BI1) {
         // BiCGSTAB, first pass of an iteration.  First iteration: p = r^ = r_0.
@@ -439,7 +445,7 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
         df[c] = eta[c] - xp[c * nvox + vox];
         xp[c * nvox + vox] = eta[c];
       }
-      acc0 += (double)frob_w(df, df);
+      acc0 += frob_acc(df, df);
     } else if (mode == XI_RESID) {
       const T* xp = (const T*)d.x;
       double r[6];
@@ -466,7 +472,7 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
         df[c] = nv - xp[c * nvox + vox];
         xp[c * nvox + vox] = nv;
       }
-      acc0 += (double)frob_w(df, df);
+      acc0 += frob_acc(df, df);
     } else if (mode == XI_PROJ) {
       // eta = -P r.  Compatible part r_c = -eta goes to the FP32 inner right-hand
       // side; the rest, r - r_c = -(incompatible part of x), is applied to x.
@@ -619,7 +625,7 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
       apply_mat<T, ISO>(mat, ph, true, rn, tau);
       apply_mat<T, ISO>(mat, ph, false, rn, cr);
       acc0 += c0_ip(d.lam0, d.mu0, rd, rd);
-      acc1 += (double)frob_w(rn, cr);
+      acc1 += frob_acc(rn, cr);
       acc2 += rd[0] * rd[0] + rd[1] * rd[1] + rd[2] * rd[2] + 2.0 * (rd[3] * rd[3] + rd[4] * rd[4] + rd[5] * rd[5]);
       if (d.h16) {
 #pragma unroll

@@ -154,7 +154,9 @@ def make_opts(scheme="cg", precision="mixed", tol=1e-8, max_iter=20000, inner_to
     o.tol, o.max_iter, o.inner_tol = tol, max_iter, inner_tol
     o.max_outer, o.check_every = max_outer, check_every
     o.autotune = 1 if autotune else 0
-    o.spectrum16 = 1 if spectrum16 else 0
+    # True / False: binary16 where the grid size and stiffness contrast allow it / never;
+    # "force": on every grid and contrast
+    o.spectrum16 = 2 if spectrum16 == "force" else 1 if spectrum16 else 0
     return o
 
 

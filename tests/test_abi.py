@@ -144,3 +144,15 @@ def test_spectrum16_limit_matches_header():
     assert m and float(m.group(1)) == ffth.SPECTRUM16_MAX_CONTRAST
     m = re.search(r"#define FFTH_SPECTRUM16_MIN_VOXELS ([0-9]+)", txt)
     assert m and int(m.group(1)) == ffth.SPECTRUM16_MIN_VOXELS
+
+
+def test_spectrum16_option_range_checked_without_device():
+    lib = ffth.load()
+    pr = _problem()
+    o = ffth.make_opts(spectrum16="force")
+    assert o.spectrum16 == 2
+    o.spectrum16 = 3
+    plan = ctypes.c_void_p()
+    st = lib.ffth_plan_create(ctypes.byref(plan), ctypes.byref(pr), ctypes.byref(o), 1, 0,
+                              ctypes.c_void_p(4096), 1 << 30, None)
+    assert st == ffth.FFTH_ERR_INVALID

@@ -44,17 +44,18 @@ def test_order2_rhs_parity(random_case):
     assert np.allclose(gm, gmean, rtol=1e-11, atol=1e-12 * np.abs(gmean).max())
 
 
-@pytest.mark.parametrize("scheme,precision", [("cg", "fp64"), ("cg", "mixed"), ("bicgstab", "fp64")])
-def test_order2_solve_parity(random_case, scheme, precision):
+@pytest.mark.parametrize("scheme,precision,h16", [("cg", "fp64", False), ("cg", "mixed", False),
+                                                  ("cg", "mixed", "force"), ("bicgstab", "fp64", False)])
+def test_order2_solve_parity(random_case, scheme, precision, h16):
     torch = require_gpu()
-    print("case order2 solve", scheme, precision, flush=True)
+    print("case order2 solve", scheme, precision, h16, flush=True)
     phase, lame, lam0, mu0, prob, corr, sols, _ = random_case
     hess = np.stack([_hessian(4), _hessian(5)])
     refs = [H.solve_order2(prob, corr, sols, h, "cg", tol=1e-13) for h in hess]
     eps0 = to_dev(torch, np.stack([voigt6(c) for c in corr]))
     eps1 = to_dev(torch, np.stack([voigt6(s) for s in sols]))
     s = ffth.Solver(phase, lam0, mu0, lame=lame, order=2, nloads=2, scheme=scheme, precision=precision,
-                    tol=1e-10)
+                    tol=1e-10, spectrum16=h16)
     eps3, res = s.solve_order2(eps0, eps1, hess.reshape(2, 54))
     eps3 = eps3.cpu().numpy()
     for l in range(2):

@@ -44,15 +44,17 @@ def hashin32_oracle():
     return phase, lame, lam0, mu0, out
 
 
-@pytest.mark.parametrize("scheme,precision", [("cg", "fp64"), ("basic", "fp64"), ("cg", "mixed")])
-def test_hashin2d_order0_parity(hashin32_oracle, scheme, precision):
+@pytest.mark.parametrize("scheme,precision,h16", [("cg", "fp64", False), ("basic", "fp64", False),
+                                                  ("cg", "mixed", False), ("cg", "mixed", "force")])
+def test_hashin2d_order0_parity(hashin32_oracle, scheme, precision, h16):
     """Sec. 4 structure at 32 x 32: strain fields and mean stresses of the three
-    in-plane unit loads equal the oracle's."""
+    in-plane unit loads equal the oracle's (also with the binary16 forward
+    spectrum forced on, as large grids run it)."""
     torch = require_gpu()
-    print("case hashin2d order0", scheme, precision, flush=True)
+    print("case hashin2d order0", scheme, precision, h16, flush=True)
     phase, lame, lam0, mu0, ref = hashin32_oracle
     s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=3, scheme=scheme, precision=precision, tol=1e-10,
-                    max_iter=20000)
+                    max_iter=20000, spectrum16=h16)
     eps, res = s.solve_order0(IN_PLANE)
     eps = eps.cpu().numpy()
     for J in range(3):

@@ -1,0 +1,132 @@
+"""GPU parity of the binary16 forward spectrum of the FP32 inner solve.  The
+plan enables it on grids of 128^3 and more; here it is forced on small grids
+so that the results can be compared with the FP64 oracle itself, under the
+same bars as the FP32-spectrum path: solves to residual 1e-10 versus the
+oracle at 1e-12, strain fields 1e-6 relative L2, effective stiffness
+|dC_IJ| <= 1e-7 sqrt(C_II C_JJ)."""
+import numpy as np
+import pytest
+
+from oracle import homogenization as H
+from paper_1712_05145_amd import ffth
+from paper_1712_05145_amd import microstructure as M
+from tests._gpu import rel_l2, require_gpu, to_dev, voigt6
+
+pytestmark = pytest.mark.gpu
+
+
+def _ceff_ok(c_gpu, c_ref, tol=1e-7):
+    d = np.sqrt(np.outer(np.diag(c_ref), np.diag(c_ref)))
+    return np.all(np.abs(c_gpu - c_ref) <= tol * d)
+
+
+@pytest.fixture(scope="module")
+def sphere16():
+    phase, lame = M.centred_sphere(16, young=(1.0, 10.0))
+    lam0, mu0 = M.midpoint_reference(lame)
+    prob = H.make_problem(phase, lam0, mu0, lame=lame)
+    ceff, corr, _ = H.effective_stiffness(prob, "cg", tol=1e-12)
+    return phase, lame, lam0, mu0, ceff, corr
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_forced_spectrum16_order0_parity_every_tile(sphere16, variant):
+    """Six unit loads in one batched call, every tile shape of every pass."""
+    torch = require_gpu()
+    print("case spectrum16 order0 variant", variant, flush=True)
+    phase, lame, lam0, mu0, ceff, corr = sphere16
+    s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, precision="mixed", tol=1e-10, spectrum16="force")
+    s.tile_variants = [variant] * 8
+    eps, res = s.solve_order0(np.eye(6))
+    eps = eps.cpu().numpy()
+    for J in range(6):
+        assert res[J]["status"] == 0 and res[J]["residual"] < 1e-10
+        assert rel_l2(eps[J], voigt6(corr[J])) < 1e-6, J
+    assert _ceff_ok(np.array([r["mean_stress"] for r in res]).T, ceff)
+
+
+@pytest.mark.parametrize("shape,seed", [((12, 16, 8), 3), ((24, 12, 32), 4), ((8, 12, 6), 5)])
+def test_forced_spectrum16_generic_stiffness_ragged(shape, seed):
+    """Non-cubic grids with ragged last tiles (n2 = 6: y-planes of 18 columns,
+    not a multiple of four, so the y-pass moves one binary16 value per
+    access), three anisotropic phases."""
+    torch = require_gpu()
+    print("case spectrum16 generic", shape, flush=True)
+    rng = np.random.default_rng(seed)
+    phase = M.random_phases(shape, 3, seed)
+    v21 = []
+    for _ in range(3):
+        a = rng.standard_normal((6, 6))
+        c = a @ a.T + 6 * np.eye(6)
+        v21.append([c[i, j] for i in range(6) for j in range(i, 6)])
+    v21 = np.array(v21)
+    lam0, mu0 = 3.0, 3.0
+    prob = H.make_problem(phase, lam0, mu0, voigt21=v21)
+    E = np.array([0.3, -1.0, 0.5, 0.2, 0.0, 1.0])
+    eps_ref, mean_ref, _ = H.solve_order0(prob, E, "cg", tol=1e-12)
+    s = ffth.Solver(phase, lam0, mu0, voigt21=v21, scheme="cg", precision="mixed", tol=1e-10,
+                    spectrum16="force")
+    eps, res = s.solve_order0(E)
+    assert res[0]["status"] == 0
+    assert rel_l2(eps[0].cpu().numpy(), voigt6(eps_ref)) < 1e-6
+    assert np.allclose(res[0]["mean_stress"], mean_ref, rtol=1e-7, atol=1e-9 * np.abs(mean_ref).max())
+
+
+def test_forced_spectrum16_order1_parity():
+    """Order-1 solve from the oracle's own correctors."""
+    torch = require_gpu()
+    print("case spectrum16 order1", flush=True)
+    phase, lame = M.centred_sphere(12, young=(1.0, 10.0))
+    lam0, mu0 = M.midpoint_reference(lame)
+    prob = H.make_problem(phase, lam0, mu0, lame=lame)
+    _, corr, _ = H.effective_stiffness(prob, "cg", tol=1e-12)
+    grad = np.zeros((6, 3))
+    grad[0, 0] = grad[1, 1] = 1.0
+    grad += 0.2 * np.random.default_rng(5).standard_normal((6, 3))
+    _, p2, _, _, _ = H.order1_rhs(prob, corr, grad)
+    eps2_ref, info = H.solve_order1(prob, corr, grad, "cg", tol=1e-12)
+    eps0 = to_dev(torch, np.stack([voigt6(c) for c in corr]))
+    s = ffth.Solver(phase, lam0, mu0, lame=lame, order=1, nloads=1, tol=1e-10, spectrum16="force")
+    eps2, res = s.solve_order1(eps0, grad.reshape(1, 18))
+    assert res[0]["status"] == 0
+    assert rel_l2(eps2[0].cpu().numpy(), voigt6(eps2_ref)) < 1e-6
+    assert np.allclose(res[0]["mean_stress"], info["mean_stress"], rtol=1e-7, atol=1e-9 * np.abs(p2).max())
+
+
+@pytest.mark.parametrize("scheme", ["cg"])
+def test_forced_spectrum16_laminate_tight_tolerance(scheme):
+    """Laminate: inner solves exact after a few iterations; the defect
+    correction still reaches 1e-12 and the Backus stiffness."""
+    torch = require_gpu()
+    layers = [0, 0, 1, 1, 1, 1, 2, 2, 0, 0, 1, 1]
+    phase = M.laminate((8, 6, 12), layers, axis=2)
+    lame = M.lame_from_young([1.0, 5.0, 2.5], [0.3, 0.25, 0.35])
+    lam0, mu0 = M.midpoint_reference(lame)
+    s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, scheme=scheme, precision="mixed", tol=1e-12,
+                    spectrum16="force")
+    _, res = s.solve_order0(np.eye(6))
+    ceff = np.array([r["mean_stress"] for r in res]).T
+    f = [np.mean(np.asarray(layers) == k) for k in range(3)]
+    ref = H.laminate_backus(lame[:, 0], lame[:, 1], f)
+    assert all(r["status"] == 0 for r in res), [r["outer_iters"] for r in res]
+    assert np.abs(ceff - ref).max() < 1e-9 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("h16", ["force", False])
+def test_tiny_and_zero_loads(h16):
+    """A zero load converges at once; a tiny load (1e-20) matches the unit
+    load: the binary16 spectrum is scaled by the right-hand side's RMS, and the
+    FP32 energy products of the inner sums are formed in FP64 (in FP32 they
+    underflow below ~1e-19 per factor)."""
+    torch = require_gpu()
+    phase, lame = M.centred_sphere(8, young=(1.0, 10.0))
+    lam0, mu0 = M.midpoint_reference(lame)
+    s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=3, precision="mixed", tol=1e-10, spectrum16=h16)
+    E = np.zeros((3, 6))
+    E[1, 0] = 1e-20
+    E[2, 0] = 1.0
+    eps, res = s.solve_order0(E)
+    assert res[0]["status"] == 0 and res[0]["iters"] == 0
+    assert torch.count_nonzero(eps[0]).item() == 0
+    assert res[1]["status"] == 0 and res[2]["status"] == 0
+    assert rel_l2(eps[1].cpu().numpy() * 1e20, eps[2].cpu().numpy()) < 1e-9

@@ -274,7 +274,8 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
         if (d.P) {
 #pragma unroll
           for (int c = 0; c < 6; ++c) pr[c] = (T)d.P[c * nvox + vox];
-        } else {
+        }
+        if (!d.P) {
           T e[6];
 #pragma unroll
           for (int c = 0; c < 6; ++c) e[c] = (T)d.E[c];
@@ -294,11 +295,15 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
       } else if (mode == XF_CG) {
         const T* rp = (const T*)d.r;
         T* pp = (T*)d.p;
-        T p[6];
+        T p[6], po[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-          const T rv = rp[c * nvox + vox];
-          p[c] = first ? rv : rv + beta * pp[c * nvox + vox];
+          p[c] = rp[c * nvox + vox];
+          po[c] = first ? T(0) : pp[c * nvox + vox];
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+          if (!first) p[c] += beta * po[c];
           pp[c * nvox + vox] = p[c];
         }
         apply_mat<T, ISO>(mat, ph, true, p, tau);
@@ -434,17 +439,19 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
     }
     if (mode == XI_STORE || mode == XI_ACCUM) {
       double* op = (double*)d.out;
+      double o[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) o[c] = (mode == XI_ACCUM && c < d.nc) ? op[c * nvox + vox] : 0.0;
 #pragma unroll
       for (int c = 0; c < 6; ++c)
-        if (c < d.nc) op[c * nvox + vox] = (mode == XI_ACCUM ? op[c * nvox + vox] : 0.0) + (double)eta[c];
+        if (c < d.nc) op[c * nvox + vox] = o[c] + (double)eta[c];
     } else if (mode == XI_BS) {
       T* xp = (T*)d.x;
       T df[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) {
-        df[c] = eta[c] - xp[c * nvox + vox];
-        xp[c * nvox + vox] = eta[c];
-      }
+      for (int c = 0; c < 6; ++c) df[c] = eta[c] - xp[c * nvox + vox];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) xp[c * nvox + vox] = eta[c];
       acc0 += frob_acc(df, df);
     } else if (mode == XI_RESID) {
       const T* xp = (const T*)d.x;
@@ -465,13 +472,14 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
     } else if (mode == XI_BS_INNER) {
       T* xp = (T*)d.x;
       const T* rp = (const T*)d.r;
-      T df[6];
+      T df[6], nv[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        const T nv = rp[c * nvox + vox] + eta[c];
-        df[c] = nv - xp[c * nvox + vox];
-        xp[c * nvox + vox] = nv;
+        nv[c] = rp[c * nvox + vox] + eta[c];
+        df[c] = nv[c] - xp[c * nvox + vox];
       }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) xp[c * nvox + vox] = nv[c];
       acc0 += frob_acc(df, df);
     } else if (mode == XI_PROJ) {
       // eta = -P r.  Compatible part r_c = -eta goes to the FP32 inner right-hand
@@ -481,11 +489,16 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
       double* xp = (double*)d.x;
       const double* rp = (const double*)d.r;
       float* op = (float*)d.out;
-      double rc[6];
+      double rc[6], xv[6], rv[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        xv[c] = xp[c * nvox + vox];
+        rv[c] = rp[c * nvox + vox];
+      }
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         rc[c] = -(double)eta[c];
-        xp[c * nvox + vox] += rp[c * nvox + vox] - rc[c];
+        xp[c * nvox + vox] = xv[c] + (rv[c] - rc[c]);
         op[c * nvox + vox] = (float)rc[c];
       }
       acc0 += rc[0] * rc[0] + rc[1] * rc[1] + rc[2] * rc[2] + 2.0 * (rc[3] * rc[3] + rc[4] * rc[4] + rc[5] * rc[5]);
@@ -499,9 +512,10 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         v[c] = pp[c * nvox + vox] - eta[c];
-        vp[c * nvox + vox] = v[c];
         h[c] = rh[c * nvox + vox];
       }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) vp[c * nvox + vox] = v[c];
       acc0 += frob_d(h, v);
     } else if (mode == XI_BI2) {
       // BiCGSTAB: t = A s = s - eta; <t,s>, <t,t>, <r^,s>, <r^,t>, <s,s>
@@ -512,10 +526,11 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         sv[c] = sp[c * nvox + vox];
-        tv[c] = sv[c] - eta[c];
-        tp[c * nvox + vox] = tv[c];
         h[c] = rh[c * nvox + vox];
+        tv[c] = sv[c] - eta[c];
       }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) tp[c * nvox + vox] = tv[c];
       acc0 += frob_d(tv, sv);
       acc1 += frob_d(tv, tv);
       acc2 += frob_d(h, sv);
@@ -526,14 +541,20 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
       T* rp = (T*)d.r;
       const T* pp = (const T*)d.p;
       double r[6];
+      T pv[6], xv[6], rv[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        const T pv = pp[c * nvox + vox];
-        const T qv = pv - eta[c];
-        xp[c * nvox + vox] += alpha * pv;
-        const T rv = rp[c * nvox + vox] - alpha * qv;
-        rp[c * nvox + vox] = rv;
-        r[c] = (double)rv;
+        pv[c] = pp[c * nvox + vox];
+        xv[c] = xp[c * nvox + vox];
+        rv[c] = rp[c * nvox + vox];
+      }
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        const T qv = pv[c] - eta[c];
+        xp[c * nvox + vox] = xv[c] + alpha * pv[c];
+        const T rn = rv[c] - alpha * qv;
+        rp[c * nvox + vox] = rn;
+        r[c] = (double)rn;
       }
       acc0 += c0_ip(d.lam0, d.mu0, r, r);
       acc1 += r[0] * r[0] + r[1] * r[1] + r[2] * r[2] + 2.0 * (r[3] * r[3] + r[4] * r[4] + r[5] * r[5]);
@@ -593,6 +614,19 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
     if (row < rows_total) {
       const long vox = row * N2 + i2;
       const int ph = d.phase[vox];
+      // every load of the voxel is issued before the first store (the output
+      // slots may alias the inputs as far as the compiler knows)
+      T rk[6], rp[6], xk[6], xp[6];
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        rk[c] = rc[c * nvox + vox];
+        if (!first) {
+          rp[c] = ro[c * nvox + vox];
+          xk[c] = xc[c * nvox + vox];
+          // x_{k-1} = x_0 = 0 at k = 1: its slot is never written in this solve
+          xp[c] = it == 1 ? T(0) : xo[c * nvox + vox];
+        }
+      }
       T rn[6];
 #pragma unroll
       for (int q = 0; q < 3; ++q) {
@@ -601,17 +635,15 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
         for (int h = 0; h < 2; ++h) {
           const int c = 2 * q + h;
           const T eta = h ? e.y : e.x;
-          const T r = rc[c * nvox + vox];
+          const T r = rk[c];
           const T w = r - eta;
           T xn, rv;
           if (first) {
             rv = r - gam * w;
             xn = gam * r;
           } else {
-            // x_{k-1} = x_0 = 0 at k = 1: its slot is never written in this solve
-            const T xold = it == 1 ? T(0) : xo[c * nvox + vox];
-            rv = om * (r - gam * w) + (T(1) - om) * ro[c * nvox + vox];
-            xn = om * (xc[c * nvox + vox] + gam * r) + (T(1) - om) * xold;
+            rv = om * (r - gam * w) + (T(1) - om) * rp[c];
+            xn = om * (xk[c] + gam * r) + (T(1) - om) * xp[c];
           }
           ro[c * nvox + vox] = rv;
           xo[c * nvox + vox] = xn;

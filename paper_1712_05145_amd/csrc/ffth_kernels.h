@@ -59,7 +59,9 @@ template <typename T> constexpr int z_cols(int n) {
 // default above, 1 and 2 halve / double the tile (or swap the block size of
 // the y-pass), within 96 KB of LDS per block; 3 keeps the x tile of 0 with one
 // wave per block (lengths whose Stockham stages have fewer butterflies than
-// the default block has threads).  The z-pass takes twice the columns (1),
+// the default block has threads; for the inverse and fused x-passes, whose
+// default is often one row, variant 1 is then two rows with 512 threads).
+// The z-pass takes twice the columns (1),
 // four times with 512 threads (2) or three times with 512 threads (3): rows
 // of >= 144 contiguous bytes in FP32.
 template <typename T> constexpr int lds_cap_rows(int n) {          // x-pass rows within 96 KB
@@ -72,7 +74,14 @@ template <typename T> constexpr int var_rows(int r0, int n, int v) {
   return r > c ? c : r;
 }
 template <typename T> constexpr int xf_rows_v(int n, int v) { return var_rows<T>(x_rows<T>(n), n, v); }
-template <typename T> constexpr int xi_rows_v(int n, int v) { return var_rows<T>(xi_rows<T>(n), n, v); }
+// inverse / fused x-pass: variant 1 of a one-row tile (nothing to halve)
+// doubles the rows with 512 threads instead
+template <typename T> constexpr bool xi_wide_v(int n, int v) {
+  return v == 1 && xi_rows<T>(n) == 1 && lds_cap_rows<T>(n) >= 2;
+}
+template <typename T> constexpr int xi_rows_v(int n, int v) {
+  return xi_wide_v<T>(n, v) ? 2 : var_rows<T>(xi_rows<T>(n), n, v);
+}
 template <typename T> constexpr int y_cols_v(int n, int v) {
   int c = y_cols<T>(n);
   if (v == 2) c = c > 1 ? c / 2 : 1;
@@ -80,6 +89,7 @@ template <typename T> constexpr int y_cols_v(int n, int v) {
 }
 template <typename T> constexpr int x_threads_v(int, int v) { return v == 3 ? 64 : NT; }
 template <typename T> constexpr int z_threads_v(int, int v) { return v >= 2 ? 512 : NT; }
+template <typename T> constexpr int xi_threads_v(int n, int v) { return xi_wide_v<T>(n, v) ? 512 : x_threads_v<T>(n, v); }
 template <typename T> constexpr int y_threads_v(int n, int v) {
   return v == 1 ? (y_threads<T>(n) == 512 ? 256 : 512) : v == 2 ? 256 : y_threads<T>(n);
 }
@@ -616,15 +626,17 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
       const int ph = d.phase[vox];
       // every load of the voxel is issued before the first store (the output
       // slots may alias the inputs as far as the compiler knows)
+      // (the iterates are streamed: each is read once per iteration, long after
+      // it was written, so the accesses carry the non-temporal hint)
       T rk[6], rp[6], xk[6], xp[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        rk[c] = rc[c * nvox + vox];
+        rk[c] = __builtin_nontemporal_load(rc + c * nvox + vox);
         if (!first) {
-          rp[c] = ro[c * nvox + vox];
-          xk[c] = xc[c * nvox + vox];
+          rp[c] = __builtin_nontemporal_load(ro + c * nvox + vox);
+          xk[c] = __builtin_nontemporal_load(xc + c * nvox + vox);
           // x_{k-1} = x_0 = 0 at k = 1: its slot is never written in this solve
-          xp[c] = it == 1 ? T(0) : xo[c * nvox + vox];
+          xp[c] = it == 1 ? T(0) : __builtin_nontemporal_load(xo + c * nvox + vox);
         }
       }
       T rn[6];
@@ -645,8 +657,8 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
             rv = om * (r - gam * w) + (T(1) - om) * rp[c];
             xn = om * (xk[c] + gam * r) + (T(1) - om) * xp[c];
           }
-          ro[c * nvox + vox] = rv;
-          xo[c * nvox + vox] = xn;
+          __builtin_nontemporal_store(rv, ro + c * nvox + vox);
+          __builtin_nontemporal_store(xn, xo + c * nvox + vox);
           rn[c] = rv;
         }
       }
@@ -699,19 +711,32 @@ __global__ __launch_bounds__(NT) void k_bicg_finish(const Desc* __restrict__ des
 // the stored values stay in range.
 // Binary16 tile transfers, G columns per access (ncols and c0 multiples of G,
 // so a group is either all inside or all outside the plane).
-template <typename T, int N1, int CW, int NTB, int G>
-__device__ __forceinline__ void y_h2_load(const H2* base, int ncols, int c0, C2<T>* buf) {
-  for (int v = threadIdx.x; v < N1 * CW / G; v += NTB) {
+// Tile loads of the y-pass: all of a thread's global loads are issued before
+// its first LDS write, so their latencies overlap.
+template <typename T, int N1, int CW, int NTB, int G, typename S>
+__device__ __forceinline__ void y_tile_load(const S* base, int ncols, int c0, C2<T>* buf) {
+  constexpr int NA = N1 * CW / G, NL = (NA + NTB - 1) / NTB;
+  C2<T> a[NL][G];
+#pragma unroll
+  for (int k = 0; k < NL; ++k) {
+    const int v = threadIdx.x + k * NTB;
     const int i1 = v / (CW / G), col = (v % (CW / G)) * G;
-    C2<T> a[G];
-    if (c0 + col < ncols) {
-      hload_g<T, G>(base + (long)i1 * ncols + col, a);
+    if ((NA % NTB == 0 || v < NA) && c0 + col < ncols) {
+      if constexpr (std::is_same<S, H2>::value) hload_g<T, G>(base + (long)i1 * ncols + col, a[k]);
+      else load_v<T, G>(base + (long)i1 * ncols + col, a[k]);
     } else {
 #pragma unroll
-      for (int q = 0; q < G; ++q) a[q] = C2<T>{0, 0};
+      for (int q = 0; q < G; ++q) a[k][q] = C2<T>{0, 0};
     }
+  }
 #pragma unroll
-    for (int q = 0; q < G; ++q) buf[i1 * CW + col + q] = a[q];
+  for (int k = 0; k < NL; ++k) {
+    const int v = threadIdx.x + k * NTB;
+    const int i1 = v / (CW / G), col = (v % (CW / G)) * G;
+    if (NA % NTB == 0 || v < NA) {
+#pragma unroll
+      for (int q = 0; q < G; ++q) buf[i1 * CW + col + q] = a[k][q];
+    }
   }
 }
 template <typename T, int N1, int CW, int NTB, int G>
@@ -737,21 +762,10 @@ __device__ __forceinline__ void ypass_body(S* base, int ncols, int c0, C2<T>* bu
   // FP32: two columns (16 bytes) per access (ncols = 6 kc is even)
   constexpr int GF = (sizeof(T) == 4 && CW % 2 == 0) ? 2 : 1;
   if constexpr (FULL) {
-    for (int v = threadIdx.x; v < N1 * CW / GF; v += NTB) {
-      const int i1 = v / (CW / GF), col = (v % (CW / GF)) * GF;
-      C2<T> a[GF];
-      if (c0 + col < ncols) {
-        load_v<T, GF>(base + (long)i1 * ncols + col, a);
-      } else {
-#pragma unroll
-        for (int q = 0; q < GF; ++q) a[q] = C2<T>{0, 0};
-      }
-#pragma unroll
-      for (int q = 0; q < GF; ++q) buf[i1 * CW + col + q] = a[q];
-    }
+    y_tile_load<T, N1, CW, NTB, GF>(base, ncols, c0, buf);
   } else {
-    if (wide) y_h2_load<T, N1, CW, NTB, G>(base, ncols, c0, buf);
-    else y_h2_load<T, N1, CW, NTB, 1>(base, ncols, c0, buf);
+    if (wide) y_tile_load<T, N1, CW, NTB, G>(base, ncols, c0, buf);
+    else y_tile_load<T, N1, CW, NTB, 1>(base, ncols, c0, buf);
   }
   __syncthreads();
   lds_fft<T, N1, CW, NTB, CW, 1, true, false, DIR, V>(buf, tw);

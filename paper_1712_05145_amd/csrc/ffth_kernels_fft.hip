@@ -49,13 +49,13 @@ static void xfwd_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, 
 }
 template <typename T, int N, int V, typename S = C2<T>>
 static void xinv_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox) {
-  constexpr int RW = ffth::xi_rows_v<T>(N, V), TB = ffth::x_threads_v<T>(N, V);
+  constexpr int RW = ffth::xi_rows_v<T>(N, V), TB = ffth::xi_threads_v<T>(N, V);
   if (iso) hipLaunchKernelGGL((k_xinv<T, N, true, RW, TB>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
   else hipLaunchKernelGGL((k_xinv<T, N, false, RW, TB>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
 }
 template <typename T, int N, int V, typename S = C2<T>>
 static void xcg3_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, long rows, long nvox) {
-  constexpr int RW = ffth::xi_rows_v<T>(N, V), TB = ffth::x_threads_v<T>(N, V);
+  constexpr int RW = ffth::xi_rows_v<T>(N, V), TB = ffth::xi_threads_v<T>(N, V);
   if (iso) hipLaunchKernelGGL((k_xcg3<T, N, true, RW, TB, S>), grid, dim3(TB), 0, s, d, rows, nvox);
   else hipLaunchKernelGGL((k_xcg3<T, N, false, RW, TB, S>), grid, dim3(TB), 0, s, d, rows, nvox);
 }

@@ -489,7 +489,8 @@ template <class F> double time_launches(hipStream_t st, hipEvent_t e0, hipEvent_
   return ms / reps;
 }
 
-template <typename T> void tune_prec(ffth_plan* P, const Desc* d, int xf_mode, int xi_mode, bool fused, bool h16) {
+template <typename T>
+void tune_prec(ffth_plan* P, const Desc* d, int nt, int xf_mode, int xi_mode, bool fused, bool h16) {
   const int pi = sizeof(T) == 8 ? 1 : 0;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return;
@@ -509,31 +510,31 @@ template <typename T> void tune_prec(ffth_plan* P, const Desc* d, int xf_mode, i
       double t;
       if (pass == PS_XF) {
         t = time_launches(P->stream, e0, e1, [&] {
-          (void)Launch<T>::xfwd(P->n[2], P->iso, v, h16, dim3(xblocks<T>(P), 1), P->stream, d, xf_mode, P->rows,
+          (void)Launch<T>::xfwd(P->n[2], P->iso, v, h16, dim3(xblocks<T>(P), nt), P->stream, d, xf_mode, P->rows,
                                 P->nvox);
         });
       } else if (pass == PS_Y) {
-        const int cw = Launch<T>::y_cols(P->n[1], v), nt = (ncols + cw - 1) / cw;
+        const int cw = Launch<T>::y_cols(P->n[1], v), ntl = (ncols + cw - 1) / cw;
         // binary16 forward spectrum: the variant serves the binary16 forward and
         // the FP32 inverse transform, so both are timed together
         t = time_launches(P->stream, e0, e1, [&] {
-          (void)Launch<T>::ypass(P->n[1], v, h16, dim3(nplanes * nt, 1), P->stream, d, -1, ncols, nt);
-          if (h16) (void)Launch<T>::ypass(P->n[1], v, false, dim3(nplanes * nt, 1), P->stream, d, +1, ncols, nt);
+          (void)Launch<T>::ypass(P->n[1], v, h16, dim3(nplanes * ntl, nt), P->stream, d, -1, ncols, ntl);
+          if (h16) (void)Launch<T>::ypass(P->n[1], v, false, dim3(nplanes * ntl, nt), P->stream, d, +1, ncols, ntl);
         });
       } else if (pass == PS_Z) {
         const int tk = Launch<T>::z_cols(P->n[0], v);
         const int nzb = (int)((M + tk - 1) / tk) * (P->h / kc);
         t = time_launches(P->stream, e0, e1, [&] {
-          (void)Launch<T>::zpass(P->n[0], v, h16, dim3(nzb, 1), P->stream, d, OP_GAMMA, P->n[1], P->h,
+          (void)Launch<T>::zpass(P->n[0], v, h16, dim3(nzb, nt), P->stream, d, OP_GAMMA, P->n[1], P->h,
                                  1.0 / (double)P->nvox);
         });
       } else if (fused) {
         t = time_launches(P->stream, e0, e1, [&] {
-          (void)Launch<T>::xcg3(P->n[2], P->iso, v, h16, dim3(iblocks<T>(P), 1), P->stream, d, P->rows, P->nvox);
+          (void)Launch<T>::xcg3(P->n[2], P->iso, v, h16, dim3(iblocks<T>(P), nt), P->stream, d, P->rows, P->nvox);
         });
       } else {
         t = time_launches(P->stream, e0, e1, [&] {
-          (void)Launch<T>::xinv(P->n[2], P->iso, v, dim3(iblocks<T>(P), 1), P->stream, d, xi_mode, P->rows, P->nvox);
+          (void)Launch<T>::xinv(P->n[2], P->iso, v, dim3(iblocks<T>(P), nt), P->stream, d, xi_mode, P->rows, P->nvox);
         });
       }
       if (t < best * (v == 0 ? 1.0 : 0.98)) {   // a variant must beat the default by 2%
@@ -573,58 +574,67 @@ ffth_status autotune(ffth_plan* P) {
     }
   }
   ffth_status s;
-  std::vector<SolverState> u(1, make_state(0, 1, 0, 1));
+  // steady-state iterations (every field of the fused CG pass is read), and
+  // launches carrying all of the plan's loads, each on its own workspace, as
+  // the solve's launches do
+  SolverState us = make_state(0, 1, 0, 1);
+  us.first = 0;
+  us.iters = 2;
+  std::vector<SolverState> u(1, us);
   if ((s = upload_states(P, u, 3 * P->nloads)) != FFTH_OK) return s;
   const Desc* dd = dptr(P, R_UTIL);
-  auto upload_one = [&](const Desc& d) -> ffth_status {
-    P->h_desc[desc_slot(P, R_UTIL, 0)] = d;
-    return upload_descs(P);
-  };
+  const int nt = P->nloads;
   const bool mixed = o.precision == FFTH_MIXED;
   if (o.precision != FFTH_FP64) {   // FP32 passes: the inner iteration (or the plain FP32 solve)
-    Desc d = base_desc(P, 0);
-    d.st = P->d_state + 3 * P->nloads;
     int xf = XF_LS, xi = XI_BS;
     bool fused = false;
-    d.x = f32_ptr(P, 0, 0);
     if (mixed && P->L.nf32 == 4) {   // three-term CG inner solve
-      d.r = f32_ptr(P, 0, 1);
-      d.x1 = f32_ptr(P, 0, 2);
-      d.r1 = f32_ptr(P, 0, 3);
       xf = XF_R3;
       fused = true;
     } else if (P->L.nf32 >= 3) {
-      d.r = f32_ptr(P, 0, 1);
-      d.p = f32_ptr(P, 0, 2);
       xf = XF_CG;
       xi = XI_CG;
     } else if (P->L.nf32 == 2) {
-      d.r = f32_ptr(P, 0, 1);
       xf = XF_MATVEC;
       xi = XI_BS_INNER;
     }
-    if (fused && P->h16) set_h16(P, d);
-    if ((s = upload_one(d)) != FFTH_OK) return s;
-    tune_prec<float>(P, dd, xf, xi, fused, fused && P->h16);
+    for (int l = 0; l < nt; ++l) {
+      Desc d = base_desc(P, l);
+      d.st = P->d_state + 3 * P->nloads;
+      d.x = f32_ptr(P, l, 0);
+      if (fused) {
+        d.r = f32_ptr(P, l, 1);
+        d.x1 = f32_ptr(P, l, 2);
+        d.r1 = f32_ptr(P, l, 3);
+        if (P->h16) set_h16(P, d);
+      } else if (P->L.nf32 >= 3) {
+        d.r = f32_ptr(P, l, 1);
+        d.p = f32_ptr(P, l, 2);
+      } else if (P->L.nf32 == 2) {
+        d.r = f32_ptr(P, l, 1);
+      }
+      P->h_desc[desc_slot(P, R_UTIL, l)] = d;
+    }
+    if ((s = upload_descs(P)) != FFTH_OK) return s;
+    tune_prec<float>(P, dd, nt, xf, xi, fused, fused && P->h16);
   }
   if (mixed || (o.precision == FFTH_FP64 && P->L.nf64 >= 2)) {   // FP64 passes
-    Desc d = base_desc(P, 0);
-    d.st = P->d_state + 3 * P->nloads;
-    int xf, xi;
-    d.x = f64_ptr(P, 0, 0);
-    if (mixed) {
-      d.r = f32_ptr(P, 0, 1);
-      d.r_f32 = 1;
-      xf = XF_LS;
-      xi = XI_RESID;
-    } else {
-      d.r = f64_ptr(P, 0, 0);
-      d.p = f64_ptr(P, 0, 1);
-      xf = XF_CG;
-      xi = XI_CG;
+    const int xf = mixed ? XF_LS : XF_CG, xi = mixed ? XI_RESID : XI_CG;
+    for (int l = 0; l < nt; ++l) {
+      Desc d = base_desc(P, l);
+      d.st = P->d_state + 3 * P->nloads;
+      d.x = f64_ptr(P, l, 0);
+      if (mixed) {
+        d.r = f32_ptr(P, l, 1);
+        d.r_f32 = 1;
+      } else {
+        d.r = f64_ptr(P, l, 0);
+        d.p = f64_ptr(P, l, 1);
+      }
+      P->h_desc[desc_slot(P, R_UTIL, l)] = d;
     }
-    if ((s = upload_one(d)) != FFTH_OK) return s;
-    tune_prec<double>(P, dd, xf, xi, false, false);
+    if ((s = upload_descs(P)) != FFTH_OK) return s;
+    tune_prec<double>(P, dd, nt, xf, xi, false, false);
   }
   HIPCHK(hipStreamSynchronize(P->stream));
   HIPCHK(hipGetLastError());

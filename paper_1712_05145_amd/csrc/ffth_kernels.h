@@ -976,7 +976,17 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
       C2<T> a[GZ];
 #pragma unroll
       for (int q = 0; q < GZ; ++q) a[q] = buf[i0 * W + w + q];
-      store_v<T, GZ>(dst + ((long)i0 * M + m0) * 6 + w, a);
+      if constexpr (FULL || TK % 4 != 0) {
+        store_v<T, GZ>(dst + ((long)i0 * M + m0) * 6 + w, a);
+      } else {
+        // the FP32 copy after the operator goes to its own buffer: streamed
+        // with the non-temporal hint, which pays only when every row segment
+        // (48 TK bytes) covers whole 64-byte chunks
+        static_assert(GZ == 2, "binary16 input implies FP32 pairs");
+        typedef float f4 __attribute__((ext_vector_type(4)));
+        const f4 o = {a[0].x, a[0].y, a[1].x, a[1].y};
+        __builtin_nontemporal_store(o, (f4*)(dst + ((long)i0 * M + m0) * 6 + w));
+      }
     }
   }
 }

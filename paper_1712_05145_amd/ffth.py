@@ -274,7 +274,10 @@ class Solver:
     """One plan over a phase field on cuda:0 (or the given device).
 
     phase: numpy/torch uint16 array (n0, n1, n2); lame: (nphases, 2) or
-    voigt21: (nphases, 21); lam0, mu0: reference medium.
+    voigt21: (nphases, 21); lam0, mu0: reference medium.  spectrum16 (mixed
+    CG): True keeps the inner solve's forward spectrum in binary16 where the
+    grid size and stiffness contrast allow it, "force" on every grid and
+    contrast, False never (options of include/ffth.h).
     """
 
     def __init__(self, phase, lam0, mu0, lame=None, voigt21=None, nloads=1, order=0, scheme="cg",

@@ -1259,6 +1259,9 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
   P->h16 = o->precision == FFTH_MIXED && o->scheme == FFTH_CG &&
            (o->spectrum16 == 2 || (o->spectrum16 == 1 && P->contrast <= FFTH_SPECTRUM16_MAX_CONTRAST &&
                                    P->nvox >= FFTH_SPECTRUM16_MIN_VOXELS));
+  // the binary16 spectrum and its FP32 copy share the load's spectrum region
+  // (sized for FP64: 48 bytes per voxel)
+  if (P->h16 && al((size_t)P->nvox * 12) + (size_t)P->nvox * 24 > L.spec_stride) P->h16 = false;
   bool ok = hip_ok(hipMemcpyAsync(P->mat64, m64.data(), m64.size() * 8, hipMemcpyHostToDevice, P->stream), "copy") &&
             hip_ok(hipMemcpyAsync(P->mat32, m32.data(), m32.size() * 4, hipMemcpyHostToDevice, P->stream), "copy");
   // phase ids must index the table

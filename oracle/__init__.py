@@ -22,8 +22,8 @@ homogenization order-0 and order-1 problems (Sec. 3, Definition 1), effective
                stiffness, Voigt/Reuss/Hashin-Shtrikman bounds
 
 Every numerical convention the paper leaves open (Nyquist modes, DFT sign,
-CG inner product, unit loads, zero-RHS guard) is fixed in ``spectral`` and
-``solvers`` docstrings and listed in DESIGN.md.
+CG inner product, unit loads, zero-RHS guard) is fixed, with its reading of
+the paper, in the ``spectral`` and ``solvers`` docstrings.
 
 Parity unpinned: the order-1 right-hand side on genuinely 3-D
 microstructures is pinned only through identities (divergence of theta,

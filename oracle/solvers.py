@@ -6,7 +6,7 @@ The discrete problem (Sec. 2): find eps with
 where P_rhs = C:E for the classical problem and p_2 + theta_2 for the
 strain-gradient problem.
 
-Readings of the paper used here (each listed in the design doc):
+Readings of the paper used here:
   * Basic Scheme: the fixed point of eq. (5), eps_{n+1} = b + eta_n with
     eta_n = -Gamma0 * ((C - C0) : eps_n), started at eps_0 = b.  (The update
     printed in Algorithm 1 would iterate eps_{n+1} = A eps_n, which diverges;

@@ -157,8 +157,8 @@ def main():
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--scheme", default="cg", choices=["cg", "basic"])
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--inner-tol", type=float, default=1e-2,
-                    help="FP32 residual reduction between FP64 reliable updates")
+    ap.add_argument("--inner-tol", type=float, default=1e-3,
+                    help="tightest FP32 residual reduction between FP64 reliable updates")
     ap.add_argument("--no-fp64", action="store_true", help="skip the FP64 comparison step")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=128)

@@ -95,7 +95,10 @@ typedef struct {
   int32_t precision;          /* ffth_precision                                        */
   double tol;                 /* relative equilibrium residual to reach (e.g. 1e-8)    */
   int32_t max_iter;           /* iterations (FP64/FP32) or total inner iterations      */
-  double inner_tol;           /* MIXED: residual reduction of each FP32 inner solve     */
+  double inner_tol;           /* MIXED: tightest residual reduction asked of one FP32
+                                 inner solve; the reduction the outer residual still
+                                 needs (half the tolerance) is split evenly over the
+                                 fewest solves that reach it at this bound            */
   int32_t max_outer;          /* MIXED: FP64 defect-correction sweeps (each sweep after
                                  the first also projects the residual onto compatible
                                  fields, one FP32 operator application)                */
@@ -108,9 +111,10 @@ typedef struct {
                                  after the operator), on grids of at least
                                  FFTH_SPECTRUM16_MIN_VOXELS voxels whose stiffness
                                  contrast (ffth_stiffness_contrast) is at most
-                                 FFTH_SPECTRUM16_MAX_CONTRAST; 2: binary16 on every
-                                 grid and contrast (more inner iterations at high
-                                 contrast); 0: FP32 throughout.  The FP64 defect
+                                 FFTH_SPECTRUM16_MAX_CONTRAST; 2: also on smaller
+                                 grids (the contrast limit still applies: above it
+                                 the perturbed inner operator can stall the inner
+                                 solves); 0: FP32 throughout.  The FP64 defect
                                  correction sets the final accuracy                    */
 } ffth_opts;
 
@@ -131,7 +135,7 @@ typedef struct {
 
 typedef struct ffth_plan ffth_plan;
 
-/* Default options: CG, MIXED, tol 1e-8, max_iter 20000, inner_tol 1e-2,
+/* Default options: CG, MIXED, tol 1e-8, max_iter 20000, inner_tol 1e-3,
  * max_outer 30, check_every 8, autotune 1, spectrum16 1. */
 void ffth_default_opts(ffth_opts *o);
 
@@ -146,7 +150,7 @@ void ffth_default_opts(ffth_opts *o);
  * Binary16 rounding (unit 2^-11) times this contrast bounds the relative error
  * a binary16 spectrum adds to the inner operator; above the limit below a
  * MIXED CG plan keeps its spectrum in FP32 whatever spectrum16 says. */
-#define FFTH_SPECTRUM16_MAX_CONTRAST 400.0
+#define FFTH_SPECTRUM16_MAX_CONTRAST 128.0
 /* Smaller grids are bound by launch latency, where binary16 saves nothing. */
 #define FFTH_SPECTRUM16_MIN_VOXELS 2097152
 double ffth_stiffness_contrast(int32_t nphases, const double *lame, const double *stiffness);

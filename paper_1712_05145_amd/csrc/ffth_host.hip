@@ -344,6 +344,7 @@ SolverState make_state(double tol, int max_iter, double guard_eps, int active) {
   SolverState s;
   std::memset(&s, 0, sizeof(s));
   s.tol = tol;
+  s.tol0 = tol;
   s.max_iter = max_iter;
   s.guard_eps = guard_eps;
   s.gscale = -1.0;
@@ -1100,7 +1101,7 @@ void ffth_default_opts(ffth_opts* o) {
   o->precision = FFTH_MIXED;
   o->tol = 1e-8;
   o->max_iter = 20000;
-  o->inner_tol = 1e-2;
+  o->inner_tol = 1e-3;
   o->max_outer = 30;
   o->check_every = 8;
   o->autotune = 1;
@@ -1256,9 +1257,9 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
   // above FFTH_SPECTRUM16_MAX_CONTRAST it would cost iterations, so FP32 is
   // kept; below FFTH_SPECTRUM16_MIN_VOXELS the launches are latency-bound
   P->contrast = stiffness_contrast(p->nphases, P->iso, p->lame, p->stiffness);
-  P->h16 = o->precision == FFTH_MIXED && o->scheme == FFTH_CG &&
-           (o->spectrum16 == 2 || (o->spectrum16 == 1 && P->contrast <= FFTH_SPECTRUM16_MAX_CONTRAST &&
-                                   P->nvox >= FFTH_SPECTRUM16_MIN_VOXELS));
+  P->h16 = o->precision == FFTH_MIXED && o->scheme == FFTH_CG && o->spectrum16 != 0 &&
+           P->contrast <= FFTH_SPECTRUM16_MAX_CONTRAST &&
+           (o->spectrum16 == 2 || P->nvox >= FFTH_SPECTRUM16_MIN_VOXELS);
   // the binary16 spectrum and its FP32 copy share the load's spectrum region
   // (sized for FP64: 48 bytes per voxel)
   if (P->h16 && al((size_t)P->nvox * 12) + (size_t)P->nvox * 24 > L.spec_stride) P->h16 = false;

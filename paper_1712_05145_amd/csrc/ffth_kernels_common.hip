@@ -19,6 +19,22 @@ __device__ static void fin_check(SolverState* st) {
 
 // Partial sums are slot-major: part[k * nblk + block].  Each op names how
 // many slots of each array it reads.
+// Reduction asked of the FP32 inner solve that starts now.  The outer residual
+// must still drop by need = 0.8 tol / res (the margin covers the FP32
+// round-off of the correction); with at most tmin per solve that takes
+// k = ceil(log need / log tmin) more solves, and the reduction is split evenly
+// over them: every solve asks for need^(1/k) >= tmin.  Fewer restarts of the
+// Krylov iteration than a fixed tmin, and no solve tighter than the sweeps
+// still ahead require.
+__device__ static double inner_target(double tmin, double outer_tol, double outer_res) {
+  if (!(outer_res > 0.0) || !(tmin > 0.0) || !(tmin < 1.0)) return tmin;
+  const double need = 0.8 * outer_tol / outer_res;
+  if (!(need < 1.0)) return fmax(tmin, 0.5);
+  if (need >= tmin) return need;
+  const double k = ceil(log(need) / log(tmin));
+  return fmax(tmin, pow(need, 1.0 / k));
+}
+
 __device__ static void fin_slots(int op, int& nf, int& ni) {
   nf = 0;
   ni = 0;
@@ -208,6 +224,7 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
       // compatible part of the FP64 residual: restart the FP32 inner solve on it
       SolverState* in = d.st2;
       st->proj++;
+      in->tol = inner_target(in->tol0, st->tol, st->res);
       in->active = si[0] > 0.0 ? 1 : 0;
       in->nb2 = si[0];
       in->dscale = si[0] > 0.0 ? sqrt(si[0] * d.inv_nvox) : 1.0;
@@ -250,6 +267,7 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
         in->active = 0;  // the projection pass sets the inner solve up
       } else {
         in->active = 1;
+        in->tol = inner_target(in->tol0, st->tol, st->res);
         in->nb2 = si[0];
         in->dscale = si[0] > 0.0 ? sqrt(si[0] * d.inv_nvox) : 1.0;
         in->rr = si[1];

@@ -28,6 +28,7 @@ struct SolverState {
   double dscale;     // inner state: RMS of the inner right-hand side (binary16 spectrum scale)
   int32_t pending;   // BiCGSTAB: x += alpha p + omega s of the last iteration not applied yet
   int32_t pad;
+  double tol0;       // inner state: the tightest reduction asked of one inner solve
 };
 
 enum : int32_t { FLAG_RUNNING = 0, FLAG_CONVERGED = 1, FLAG_DIVERGED = 2, FLAG_ZERO_RHS = 3 };

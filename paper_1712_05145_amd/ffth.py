@@ -145,7 +145,7 @@ def _darr(a):
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 
 
-def make_opts(scheme="cg", precision="mixed", tol=1e-8, max_iter=20000, inner_tol=1e-2, max_outer=30,
+def make_opts(scheme="cg", precision="mixed", tol=1e-8, max_iter=20000, inner_tol=1e-3, max_outer=30,
               check_every=8, autotune=True, spectrum16=True):
     o = ffth_opts()
     load().ffth_default_opts(ctypes.byref(o))
@@ -155,7 +155,7 @@ def make_opts(scheme="cg", precision="mixed", tol=1e-8, max_iter=20000, inner_to
     o.max_outer, o.check_every = max_outer, check_every
     o.autotune = 1 if autotune else 0
     # True / False: binary16 where the grid size and stiffness contrast allow it / never;
-    # "force": on every grid and contrast
+    # "force": on grids of any size (the contrast limit still applies)
     o.spectrum16 = 2 if spectrum16 == "force" else 1 if spectrum16 else 0
     return o
 
@@ -175,7 +175,7 @@ def ffth_size_supported(n):
     return bool(load().ffth_size_supported(int(n)))
 
 
-SPECTRUM16_MAX_CONTRAST = 400.0   # FFTH_SPECTRUM16_MAX_CONTRAST
+SPECTRUM16_MAX_CONTRAST = 128.0   # FFTH_SPECTRUM16_MAX_CONTRAST
 SPECTRUM16_MIN_VOXELS = 128 ** 3   # FFTH_SPECTRUM16_MIN_VOXELS
 
 
@@ -276,12 +276,12 @@ class Solver:
     phase: numpy/torch uint16 array (n0, n1, n2); lame: (nphases, 2) or
     voigt21: (nphases, 21); lam0, mu0: reference medium.  spectrum16 (mixed
     CG): True keeps the inner solve's forward spectrum in binary16 where the
-    grid size and stiffness contrast allow it, "force" on every grid and
-    contrast, False never (options of include/ffth.h).
+    grid size and stiffness contrast allow it, "force" on grids of any size
+    (within the contrast limit), False never (options of include/ffth.h).
     """
 
     def __init__(self, phase, lam0, mu0, lame=None, voigt21=None, nloads=1, order=0, scheme="cg",
-                 precision="mixed", tol=1e-8, max_iter=20000, inner_tol=1e-2, max_outer=30, check_every=8,
+                 precision="mixed", tol=1e-8, max_iter=20000, inner_tol=1e-3, max_outer=30, check_every=8,
                  autotune=True, spectrum16=True, device="cuda:0", stream=None):
         import torch
         self.torch = torch

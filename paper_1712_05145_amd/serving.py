@@ -15,7 +15,7 @@ from . import ffth
 
 
 class Server:
-    def __init__(self, budget_bytes, max_running=32, tol=1e-8, inner_tol=1e-2, check_every=8, max_iter=20000,
+    def __init__(self, budget_bytes, max_running=32, tol=1e-8, inner_tol=1e-3, check_every=8, max_iter=20000,
                  device="cuda:0", stream=None):
         import torch
         self.torch = torch

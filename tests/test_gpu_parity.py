@@ -388,9 +388,9 @@ def test_spectrum16_agrees_with_fp32_spectrum_and_is_gated():
     grids below the size limit, the plan keeps FP32, so switching the option
     changes nothing (bit-identical results)."""
     torch = require_gpu()
-    low = M.random_spheres(128, 6, seed=3)                    # Young 1 / 100: contrast 325
-    high = M.overlapping_spheres(128, 0.25, 500.0, 7)         # contrast 1625
-    small = M.random_spheres(64, 6, seed=3)
+    low = M.random_spheres(128, 6, seed=3, young=(1.0, 20.0))   # contrast 65
+    high = M.overlapping_spheres(128, 0.25, 500.0, 7)           # contrast 1625
+    small = M.random_spheres(64, 6, seed=3, young=(1.0, 20.0))
     assert ffth.ffth_stiffness_contrast(lame=low[1]) <= ffth.SPECTRUM16_MAX_CONTRAST
     assert ffth.ffth_stiffness_contrast(lame=high[1]) > ffth.SPECTRUM16_MAX_CONTRAST
     assert low[0].size >= ffth.SPECTRUM16_MIN_VOXELS > small[0].size

@@ -38,7 +38,7 @@ def test_alone_equals_mix_and_plan_path():
     the plan path."""
     torch = require_gpu()
     from paper_1712_05145_amd.serving import Server
-    a = _req(128, 0.25, 50.0, 1)
+    a = _req(128, 0.25, 20.0, 1)
     others = [_req(64, 0.3, 200.0, 2), _req(48, 0.2, 10.0, 3), _req(128, 0.35, 400.0, 4), _req(64, 0.1, 5.0, 5)]
     lim = ffth.SPECTRUM16_MAX_CONTRAST
     assert ffth.ffth_stiffness_contrast(lame=a[1]) <= lim < ffth.ffth_stiffness_contrast(lame=others[2][1])

@@ -381,6 +381,23 @@ def test_mixed_three_term_inner_iterations_track_fp64_cg():
     assert its["mixed"] <= 1.3 * its["fp64"] + 12
 
 
+@pytest.mark.parametrize("tol,sweeps", [(1e-8, 4), (1e-10, 5), (1e-5, 3)])
+def test_inner_targets_split_the_reduction(tol, sweeps):
+    """The inner solves split the reduction the outer residual still needs over
+    the fewest solves at the 1e-3 bound: ceil(log(0.8 tol) / log 1e-3) of them,
+    so the FP64 applications per load are at most that count plus the right-hand
+    side's (a solve that overshoots its target can save one)."""
+    torch = require_gpu()
+    print("case inner targets", tol, flush=True)
+    phase, lame = M.random_spheres(32, 6, seed=3, young=(1.0, 20.0))
+    lam0, mu0 = M.midpoint_reference(lame)
+    s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, precision="mixed", tol=tol, inner_tol=1e-3)
+    _, res = s.solve_order0(np.eye(6))
+    print("fp64 applications", [r["fp64_applications"] for r in res], flush=True)
+    assert all(r["status"] == 0 and r["residual"] < tol for r in res)
+    assert all(r["fp64_applications"] <= sweeps for r in res)
+
+
 def test_spectrum16_agrees_with_fp32_spectrum_and_is_gated():
     """Binary16 forward spectrum in the inner solve (128^3): same effective
     stiffness to the solve's accuracy and about the same iterations as the FP32

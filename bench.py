@@ -298,6 +298,17 @@ def main():
                 "avg_launch_ms": round(tot_ms / max(launches, 1), 4),
                 "copy_GBs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
 
+    # one FP32 inner iteration of one load over its four passes (fused CG pass,
+    # forward y, z with the Green operator, inverse y): algorithmic bytes per
+    # voxel and the per-load times of the same timed steps
+    it_ms = {c: prof[c][1] / max(prof[c][2], 1) for c in ("xcg3_f32", "ypass_f32", "zpass_f32")}
+    it_ms_total = it_ms["xcg3_f32"] + 2 * it_ms["ypass_f32"] + it_ms["zpass_f32"]
+    it_bpv = ab["xcg3"] + ab["yf"] + ab["yi"] + ab["z"]
+    inner_iteration = {"alg_bytes_per_voxel": it_bpv, "ms_per_load": round(it_ms_total, 4),
+                       "achieved_GBs": round(it_bpv * nvox / (it_ms_total * 1e-3) / 1e9, 1) if it_ms_total > 0 else None,
+                       "frac_of_peak": round(it_bpv * nvox / (it_ms_total * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                       if it_ms_total > 0 else None}
+
     line = {
         "metric": METRIC, "value": round(value, 1), "unit": "voxel-iters/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": round(ms_step, 2), "higher_is_better": True, "scaling": "weak",
@@ -312,6 +323,7 @@ def main():
         "latency_ms": {"p50": round(float(np.percentile(times, 50)) * 1e3, 2),
                        "p99": round(float(np.percentile(times, 99)) * 1e3, 2), "over": "timed steps"},
         "roofline": roofline,
+        "inner_iteration": inner_iteration,
         "kernels": kernels,
         "tile_variants": dict(zip(["xfwd_f32", "xfwd_f64", "ypass_f32", "ypass_f64", "zpass_f32", "zpass_f64",
                                    "xinv_f32", "xinv_f64"], s0.tile_variants)),

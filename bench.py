@@ -109,6 +109,38 @@ def cpu_baseline(n_sample, grains, seed):
                       f"{n_sample}^3 Voronoi polycrystal of the same generator, single thread, {dt:.1f} s"}
 
 
+def spheres128_run(dev):
+    """Random-sphere composite at 128^3 (20 non-overlapping spheres, Young
+    contrast 100, nu 0.3): the six unit loads with the Basic Scheme and with CG,
+    FP32 inner solves under FP64 defect correction to 1e-8."""
+    import torch
+
+    from paper_1712_05145_amd import ffth
+    from paper_1712_05145_amd import microstructure as M
+    phase, lame = M.random_spheres(128, 20, seed=2)
+    lam0, mu0 = M.midpoint_reference(lame)
+    out, ceffs = {}, {}
+    for scheme in ("cg", "basic"):
+        s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, scheme=scheme, precision="mixed", tol=1e-8,
+                        max_iter=50000, device=dev)
+        s.solve_order0(np.eye(6))                        # warm-up (tile tuning, first launches)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, res = s.solve_order0(np.eye(6))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        apps = sum(r["iters"] + r["projections"] + r["fp64_applications"] for r in res)
+        out[scheme] = {"ms": round(dt * 1e3, 2), "fp32_inner": sum(r["iters"] for r in res),
+                       "fp64_applications": sum(r["fp64_applications"] for r in res),
+                       "voxel_iters_per_s": round(phase.size * apps / dt, 1)}
+        ceffs[scheme] = np.array([r["mean_stress"] for r in res]).T
+        s.close()
+    d = np.sqrt(np.outer(np.diag(ceffs["cg"]), np.diag(ceffs["cg"])))
+    out["ceff_cg_vs_basic_max_scaled_diff"] = float(np.max(np.abs(ceffs["cg"] - ceffs["basic"]) / d))
+    log(f"spheres128: CG {out['cg']['ms']} ms, Basic Scheme {out['basic']['ms']} ms")
+    return out
+
+
 def serving_run(count, rate, dev):
     """Request stream: Poisson arrivals, grids 32^3..128^3, random-sphere
     microstructures, six unit loads each, mixed CG to 1e-8, 64 GB arena."""
@@ -163,6 +195,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-n", type=int, default=128)
     ap.add_argument("--no-serve", action="store_true", help="skip the request-stream (serving) measurement")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 128^3 random-sphere measurement")
     ap.add_argument("--serve-count", type=int, default=512)
     ap.add_argument("--serve-rate", type=float, default=40.0)
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
@@ -376,6 +409,8 @@ def main():
         log(f"bicgstab fp64 step {tbi * 1e3:.1f} ms, C_eff diff {diffb.max():.2e}")
         del b0, b1, e0, e1
         torch.cuda.empty_cache()
+    if not args.no_configs:
+        line["spheres128"] = spheres128_run(dev)
     if not args.no_serve:
         line["serving"] = serving_run(args.serve_count, args.serve_rate, dev)
     if not args.no_cpu:

@@ -146,7 +146,7 @@ void ffth_default_opts(ffth_opts *o);
  * 2 mu and five times 2 mu for isotropic phases).  lame: HOST nphases x 2, or
  * NULL and stiffness: HOST nphases x 21 Voigt upper triangle.  Returns
  * INFINITY when a phase is not positive definite, and NAN for bad arguments
- * (nphases < 1, both tables NULL).  Host only; no device is touched.
+ * (nphases < 1, both tables NULL, a coefficient that is not a number).  Host only; no device is touched.
  * Binary16 rounding (unit 2^-11) times this contrast bounds the relative error
  * a binary16 spectrum adds to the inner operator; above the limit below a
  * MIXED CG plan keeps its spectrum in FP32 whatever spectrum16 says. */

@@ -186,6 +186,7 @@ double stiffness_contrast(int nph, bool iso, const double* lame, const double* v
       sym6_eigenvalues(a, ev);
     }
     for (int i = 0; i < 6; ++i) {
+      if (!(ev[i] == ev[i])) return NAN;   // a coefficient that is not a number
       lo = std::min(lo, ev[i]);
       hi = std::max(hi, ev[i]);
     }

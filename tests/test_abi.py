@@ -134,6 +134,10 @@ def test_stiffness_contrast_matches_eigenvalues():
     assert abs(ffth.ffth_stiffness_contrast(voigt21=np.array(iso21)) - ffth.ffth_stiffness_contrast(lame=lame)) \
         < 1e-9 * ffth.ffth_stiffness_contrast(lame=lame)
     assert ffth.ffth_stiffness_contrast(lame=[[1.0, -0.1]]) == np.inf          # not positive definite
+    assert np.isnan(ffth.ffth_stiffness_contrast(lame=[[1.0, 1.0], [np.nan, 1.0]]))
+    bad = v.copy()
+    bad[1, 4] = np.nan
+    assert np.isnan(ffth.ffth_stiffness_contrast(voigt21=bad))
     lib = ffth.load()
     assert np.isnan(lib.ffth_stiffness_contrast(0, None, None))
 

@@ -807,8 +807,11 @@ ffth_status group_round(std::vector<Job*>& jobs, Stage& st) {
   const ffth_opts& o = dims->opts;
   ffth_status s;
   for (Job* J : jobs) {
-    // one launch serves every job: a binary16 kernel needs the FP32 copy
-    // (spec2) that only binary16 descriptors carry, and the tiles must agree
+    // one launch serves every job, with the first job's kernels: a binary16
+    // kernel needs the FP32 copy (spec2) that only binary16 descriptors carry.
+    // Tile shapes come from the first job's plan too; every plan's partial
+    // sums are sized for the largest block count of any shape, and plans of
+    // one grid, material kind, precision and scheme share the tuned shapes.
     const ffth_plan* P = J->P;
     if (P->n[0] != dims->n[0] || P->n[1] != dims->n[1] || P->n[2] != dims->n[2] || P->iso != dims->iso ||
         P->h16 != dims->h16 || P->opts.scheme != o.scheme) {

@@ -1,0 +1,62 @@
+"""Host logic of bench.py: the algorithmic byte model behind the roofline and
+the gate that reports measured HBM traffic only for the kernel sources the
+counters were taken on.  CPU only."""
+import os
+import shutil
+
+import pytest
+
+import bench
+
+# Field sizes per voxel and load (the half spectrum holds n/2 of n complex
+# values per component, so a spectrum is as large as the real field).
+COMP = 6
+F32 = COMP * 4            # one FP32 6-component field (or FP32 half spectrum)
+H16 = COMP * 2            # binary16 half spectrum
+IDS = 2                   # uint16 phase id
+
+
+def test_inner_iteration_byte_model_from_its_streams():
+    m16 = bench.alg_bytes_per_voxel(True)
+    m32 = bench.alg_bytes_per_voxel(False)
+    # forward y-pass: binary16 spectrum read and written (FP32 without it)
+    assert m16["yf"] == H16 + H16 and m32["yf"] == F32 + F32
+    # inverse y-pass: FP32 spectrum read and written in both cases
+    assert m16["yi"] == m32["yi"] == F32 + F32
+    # z-pass: binary16 in, FP32 copy out (FP32 in place without it)
+    assert m16["z"] == H16 + F32 and m32["z"] == F32 + F32
+    # fused CG pass: FP32 spectrum, r_k, x_k, r_k-1, x_k-1, ids read;
+    # r_k+1, x_k+1 and the next forward spectrum written
+    reads = F32 + 4 * F32 + IDS
+    assert m16["xcg3"] == reads + 2 * F32 + H16
+    assert m32["xcg3"] == reads + 2 * F32 + F32
+    # start pass: r_0 and ids read, forward spectrum written
+    assert m16["start"] == F32 + IDS + H16 and m32["start"] == F32 + IDS + F32
+    # the first two iterations of a solve skip x_k, r_k-1, x_k-1 (72 B) and x_k-1 (24 B)
+    assert bench.XCG3_START_SAVING == 3 * F32 + F32
+    # one inner iteration of a load: four passes
+    assert m16["xcg3"] + m16["yf"] + m16["z"] + m16["yi"] == 290.0
+
+
+def _copy_tree(dst):
+    root = bench.ROOT
+    shutil.copytree(os.path.join(root, "paper_1712_05145_amd", "csrc"),
+                    os.path.join(dst, "paper_1712_05145_amd", "csrc"))
+    shutil.copytree(os.path.join(root, "profiles"), os.path.join(dst, "profiles"))
+
+
+def test_traffic_reported_only_for_the_profiled_sources(tmp_path, monkeypatch):
+    if bench.measured_traffic("xcg3_f32") is None:
+        pytest.skip("kernel sources changed since the counter summary was taken")
+    _copy_tree(str(tmp_path))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    value = bench.measured_traffic("xcg3_f32")
+    assert value is not None and value > 0
+    # any change to a kernel source voids the recorded traffic
+    src = os.path.join(str(tmp_path), "paper_1712_05145_amd", "csrc", "ffth_kernels.h")
+    with open(src, "a") as f:
+        f.write("\n")
+    assert bench.measured_traffic("xcg3_f32") is None
+    # and without the summary there is nothing to report
+    os.remove(os.path.join(str(tmp_path), "profiles", "traffic_fp32_passes_voronoi256.md"))
+    assert bench.measured_traffic("xcg3_f32") is None

@@ -252,6 +252,42 @@ def laminate_backus(lam, mu, fractions):
     return c
 
 
+def laminate_layers_voigt(c66_layers, fractions):
+    """Effective Voigt stiffness (engineering shear) of a laminate of
+    anisotropic layers normal to x3, from the layers' 6x6 Voigt matrices.
+
+    Across the layers the traction (sigma_33, sigma_23, sigma_13) and the
+    in-plane engineering strains (eps_11, eps_22, gamma_12) are uniform.  With
+    the Voigt indices split into N = (33, 23, 13) and T = (11, 22, 12), each
+    layer gives e_N = C_NN^-1 (s_N - C_NT e_T) and
+    s_T = (C_TT - C_TN C_NN^-1 C_NT) e_T + C_TN C_NN^-1 s_N; averaging e_N
+    and s_T over the layers yields
+      C*_NN = <C_NN^-1>^-1,          C*_NT = C*_NN <C_NN^-1 C_NT>,
+      C*_TT = <C_TT - C_TN C_NN^-1 C_NT> + <C_TN C_NN^-1> C*_NN <C_NN^-1 C_NT>.
+    For isotropic layers this reduces to laminate_backus."""
+    c = np.asarray(c66_layers, dtype=np.float64).reshape(-1, 6, 6)
+    f = np.asarray(fractions, dtype=np.float64)
+    N, T = [2, 3, 4], [0, 1, 5]
+    cnn = c[:, N][:, :, N]
+    cnt = c[:, N][:, :, T]
+    ctn = c[:, T][:, :, N]
+    ctt = c[:, T][:, :, T]
+    inv = np.linalg.inv(cnn)
+
+    def avg(a):
+        return np.einsum("l,l...->...", f, a)
+
+    snn = np.linalg.inv(avg(inv))
+    a_nt = avg(inv @ cnt)
+    a_tn = avg(ctn @ inv)
+    out = np.zeros((6, 6))
+    out[np.ix_(N, N)] = snn
+    out[np.ix_(N, T)] = snn @ a_nt
+    out[np.ix_(T, N)] = a_tn @ snn
+    out[np.ix_(T, T)] = avg(ctt - ctn @ inv @ cnt) + a_tn @ snn @ a_nt
+    return out
+
+
 def laminate_1d_solve(ctens_profile, pol_profile):
     """Exact discrete solution for a laminate whose data vary along x3 only.
 

@@ -70,15 +70,21 @@ typedef enum {
 } ffth_status;
 
 /* FFTH_BICGSTAB: BiCGSTAB on eq. (6), the Krylov method of the paper's
- * experiments (Sec. 4); FP64 or FP32 precision only. */
-typedef enum { FFTH_BASIC = 0, FFTH_CG = 1, FFTH_BICGSTAB = 2 } ffth_scheme;
+ * experiments (Sec. 4); FP64 or FP32 precision only.
+ * FFTH_CG3: CG on eq. (6) in the C0 inner product through the three-term
+ * (Rutishauser) recurrence, started from eps_0 = 0: the same iterates as
+ * two-term CG from zero in exact arithmetic, one HBM pass fewer per
+ * iteration (the update, its reductions and the next polarization share one
+ * pass); FP64 or FP32 precision only (FFTH_MIXED runs it inside its FP32
+ * inner solves already). */
+typedef enum { FFTH_BASIC = 0, FFTH_CG = 1, FFTH_BICGSTAB = 2, FFTH_CG3 = 3 } ffth_scheme;
 typedef enum { FFTH_FP64 = 0, FFTH_FP32 = 1, FFTH_MIXED = 2 } ffth_precision;
 
 /* The cell problem of Sec. 2: stiffness field C(x) = table[phase[x]] with
  * major and minor symmetries, and the isotropic reference medium C0 with
  * Lame parameters (lambda0, mu0).  mu0 != 0 and lambda0 + 2 mu0 != 0 are
  * required (the Green operator formula below eq. (5) divides by both); the
- * CG scheme also needs mu0 > 0 and 3 lambda0 + 2 mu0 > 0 (positive C0). */
+ * CG schemes also need mu0 > 0 and 3 lambda0 + 2 mu0 > 0 (positive C0). */
 typedef struct {
   int32_t n[3];               /* voxels per axis                                       */
   int32_t nphases;            /* entries in the phase table (1..65535)                 */
@@ -241,10 +247,10 @@ ffth_status ffth_order1_rhs(ffth_plan *plan, const double *eps0_six, const doubl
 
 /* Kernel timing (diagnostics).  When enabled, every kernel launch of the plan
  * is bracketed by HIP events recorded on the plan's stream; the totals per
- * kernel category (0 .. 11: x-pass forward / y-pass / z-pass / x-pass inverse
+ * kernel category (0 .. 13: x-pass forward / y-pass / z-pass / x-pass inverse
  * in FP32, the same four in FP64, finalize, pointwise, fused three-term CG
- * x-pass, its start pass) accumulate until the next ffth_profile_enable call, which also
- * resets them.  launches: kernel launches; units: batch entries (loads) they
+ * x-pass and its start pass in FP32, the same two in FP64) accumulate until
+ * the next ffth_profile_enable call, which also resets them.  launches: kernel launches; units: batch entries (loads) they
  * processed, summed; ms: summed event time. */
 ffth_status ffth_profile_enable(ffth_plan *plan, int32_t on);
 ffth_status ffth_profile_read(ffth_plan *plan, int32_t category, int64_t *launches, int64_t *units,

@@ -27,6 +27,12 @@ class FreeList {
     }
     return false;
   }
+  // True when alloc(need) would succeed (nothing is taken).
+  bool fits(size_t need) const {
+    for (const auto& kv : free_)
+      if (kv.second >= need) return true;
+    return false;
+  }
   // Give [off, off + len) back, merging with free neighbours.  A range that
   // overlaps free space was never handed out (or is returned twice): it is
   // refused, so that no byte can be handed out twice.

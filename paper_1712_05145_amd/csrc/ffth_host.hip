@@ -20,7 +20,9 @@
 #include <string>
 #include <vector>
 
+#include "admission.h"
 #include "arena.h"
+#include "desc_check.h"
 #include "ffth.h"
 #include "ffth_launch.h"
 #include "ffth_types.h"
@@ -74,9 +76,10 @@ Layout make_layout(const int n[3], int nph, int nloads, int order, const ffth_op
   L.nstate = 3 * nloads + 1;
   L.nblk = std::max((int)((long)n[0] * n[1]), ms_blocks(nvox));   // x-pass blocks of any variant (>= 1 row)
   // per-load FP32 / FP64 field counts
-  if (prec == FFTH_FP32) L.nf32 = scheme == FFTH_CG ? 3 : scheme == FFTH_BICGSTAB ? 7 : 1;
-  if (prec == FFTH_MIXED) L.nf32 = scheme == FFTH_CG ? 4 : 2;   // three-term CG: x, r in two slots each
-  if (prec == FFTH_FP64) L.nf64 = scheme == FFTH_CG ? 2 : scheme == FFTH_BICGSTAB ? 6 : 0;
+  // three-term CG (the mixed inner solve and FFTH_CG3): x, r in two slots each
+  if (prec == FFTH_FP32) L.nf32 = scheme == FFTH_CG ? 3 : scheme == FFTH_BICGSTAB ? 7 : scheme == FFTH_CG3 ? 4 : 1;
+  if (prec == FFTH_MIXED) L.nf32 = scheme == FFTH_CG ? 4 : 2;
+  if (prec == FFTH_FP64) L.nf64 = scheme == FFTH_CG ? 2 : scheme == FFTH_BICGSTAB ? 6 : scheme == FFTH_CG3 ? 4 : 0;
   if (prec == FFTH_MIXED) L.nf64 = 1;   // FP64 residual before its compatible projection
   L.spec_stride = al((size_t)nvox * 6 * sizeof(double));     // 6 x (nvox/2) complex FP64
   L.f32_stride = al((size_t)nvox * 6 * sizeof(float));
@@ -106,8 +109,9 @@ Layout make_layout(const int n[3], int nph, int nloads, int order, const ffth_op
 }
 
 bool opts_valid(const ffth_opts& o) {
-  if (o.scheme != FFTH_BASIC && o.scheme != FFTH_CG && o.scheme != FFTH_BICGSTAB) return false;
-  if (o.scheme == FFTH_BICGSTAB && o.precision == FFTH_MIXED) return false;   // FP64 or FP32 only
+  if (o.scheme != FFTH_BASIC && o.scheme != FFTH_CG && o.scheme != FFTH_BICGSTAB && o.scheme != FFTH_CG3) return false;
+  // FP64 or FP32 only
+  if ((o.scheme == FFTH_BICGSTAB || o.scheme == FFTH_CG3) && o.precision == FFTH_MIXED) return false;
   if (o.precision < FFTH_FP64 || o.precision > FFTH_MIXED) return false;
   if (!(o.tol > 0.0) || o.max_iter < 1 || o.check_every < 1) return false;
   if (o.precision == FFTH_MIXED && (!(o.inner_tol > 0.0) || o.inner_tol >= 1.0 || o.max_outer < 1)) return false;
@@ -273,10 +277,13 @@ const Desc* dptr(ffth_plan* P, Role r) { return P->d_desc + desc_slot(P, r, 0); 
 int util6_slot(ffth_plan* P, int J) { return 7 * P->nloads + J; }
 
 // ---- kernel timing ---------------------------------------------------------
-enum Cat { C_XF32 = 0, C_Y32, C_Z32, C_XI32, C_XF64, C_Y64, C_Z64, C_XI64, C_FIN, C_POINT, C_XCG3, C_CG3S, NCAT };
+enum Cat {
+  C_XF32 = 0, C_Y32, C_Z32, C_XI32, C_XF64, C_Y64, C_Z64, C_XI64, C_FIN, C_POINT, C_XCG3, C_CG3S, C_XCG3_64,
+  C_CG3S_64, NCAT
+};
 const char* const CAT_NAMES[NCAT] = {"xfwd_f32", "ypass_f32", "zpass_f32", "xinv_f32", "xfwd_f64",
                                      "ypass_f64", "zpass_f64", "xinv_f64", "finalize", "pointwise",
-                                     "xcg3_f32", "cg3start_f32"};
+                                     "xcg3_f32", "cg3start_f32", "xcg3_f64", "cg3start_f64"};
 
 hipEvent_t take_event(ffth_plan* P) {
   if (P->pool.empty()) {
@@ -388,7 +395,7 @@ template <typename T> int xblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->nx6
 template <typename T> int iblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->ni64 : P->ni32; }
 
 template <typename T> ffth_status xfwd(ffth_plan* P, const Desc* d, int nb, int mode, bool h16 = false) {
-  ProfScope ps(P, sizeof(T) == 8 ? C_XF64 : mode == XF_R3 ? C_CG3S : C_XF32, nb);
+  ProfScope ps(P, mode == XF_R3 ? (sizeof(T) == 8 ? C_CG3S_64 : C_CG3S) : sizeof(T) == 8 ? C_XF64 : C_XF32, nb);
   HIPCHK(Launch<T>::xfwd(P->n[2], P->iso, pv<T>(P, PS_XF), h16, dim3(xblocks<T>(P), nb), P->stream, d, mode, P->rows,
                          P->nvox));
   return FFTH_OK;
@@ -443,25 +450,26 @@ ffth_status fin(ffth_plan* P, const Desc* d, int nb, int op, int nblk_f, int nbl
   return FFTH_OK;
 }
 
-// Start of a three-term CG inner solve: tau(r_0), its x-transform and the scalars.
-ffth_status cg3_start(ffth_plan* P, const Desc* d, int nb) {
+// Start of a three-term CG solve: tau(r_0), its x-transform and the scalars.
+// h16: the binary16-spectrum kernels (FP32 inner solves of a binary16 plan).
+template <typename T> ffth_status cg3_start(ffth_plan* P, const Desc* d, int nb, bool h16) {
   ffth_status s;
   if (nb <= 0) return FFTH_OK;
-  if ((s = xfwd<float>(P, d, nb, XF_R3, P->h16)) != FFTH_OK) return s;
-  return fin(P, d, nb, FIN_CG3_INIT, xblocks<float>(P), 0);
+  if ((s = xfwd<T>(P, d, nb, XF_R3, h16)) != FFTH_OK) return s;
+  return fin(P, d, nb, FIN_CG3_INIT, xblocks<T>(P), 0);
 }
 
 // One three-term CG iteration: y, z (Green operator), y, fused x-pass, scalars.
-ffth_status cg3_iter(ffth_plan* P, const Desc* d, int nb) {
+template <typename T> ffth_status cg3_iter(ffth_plan* P, const Desc* d, int nb, bool h16) {
   ffth_status s;
   if (nb <= 0) return FFTH_OK;
-  if ((s = yzy<float>(P, d, nb, OP_GAMMA, P->h16)) != FFTH_OK) return s;
+  if ((s = yzy<T>(P, d, nb, OP_GAMMA, h16)) != FFTH_OK) return s;
   {
-    ProfScope ps(P, C_XCG3, nb);
-    HIPCHK(Launch<float>::xcg3(P->n[2], P->iso, pv<float>(P, PS_XI), P->h16, dim3(iblocks<float>(P), nb), P->stream, d,
-                               P->rows, P->nvox));
+    ProfScope ps(P, sizeof(T) == 8 ? C_XCG3_64 : C_XCG3, nb);
+    HIPCHK(Launch<T>::xcg3(P->n[2], P->iso, pv<T>(P, PS_XI), h16, dim3(iblocks<T>(P), nb), P->stream, d, P->rows,
+                           P->nvox));
   }
-  return fin(P, d, nb, FIN_CG3, 0, iblocks<float>(P));
+  return fin(P, d, nb, FIN_CG3, 0, iblocks<T>(P));
 }
 
 // ---- autotuner ------------------------------------------------------------
@@ -590,7 +598,7 @@ ffth_status autotune(ffth_plan* P) {
   if (o.precision != FFTH_FP64) {   // FP32 passes: the inner iteration (or the plain FP32 solve)
     int xf = XF_LS, xi = XI_BS;
     bool fused = false;
-    if (mixed && P->L.nf32 == 4) {   // three-term CG inner solve
+    if ((mixed && P->L.nf32 == 4) || o.scheme == FFTH_CG3) {   // three-term CG (inner) solve
       xf = XF_R3;
       fused = true;
     } else if (P->L.nf32 >= 3) {
@@ -621,7 +629,8 @@ ffth_status autotune(ffth_plan* P) {
     tune_prec<float>(P, dd, nt, xf, xi, fused, fused && P->h16);
   }
   if (mixed || (o.precision == FFTH_FP64 && P->L.nf64 >= 2)) {   // FP64 passes
-    const int xf = mixed ? XF_LS : XF_CG, xi = mixed ? XI_RESID : XI_CG;
+    const bool cg3 = o.scheme == FFTH_CG3;
+    const int xf = mixed ? XF_LS : cg3 ? XF_R3 : XF_CG, xi = mixed ? XI_RESID : XI_CG;
     for (int l = 0; l < nt; ++l) {
       Desc d = base_desc(P, l);
       d.st = P->d_state + 3 * P->nloads;
@@ -629,6 +638,10 @@ ffth_status autotune(ffth_plan* P) {
       if (mixed) {
         d.r = f32_ptr(P, l, 1);
         d.r_f32 = 1;
+      } else if (cg3) {
+        d.r = f64_ptr(P, l, 1);
+        d.x1 = f64_ptr(P, l, 2);
+        d.r1 = f64_ptr(P, l, 3);
       } else {
         d.r = f64_ptr(P, l, 0);
         d.p = f64_ptr(P, l, 1);
@@ -636,7 +649,7 @@ ffth_status autotune(ffth_plan* P) {
       P->h_desc[desc_slot(P, R_UTIL, l)] = d;
     }
     if ((s = upload_descs(P)) != FFTH_OK) return s;
-    tune_prec<double>(P, dd, nt, xf, xi, false, false);
+    tune_prec<double>(P, dd, nt, xf, xi, cg3, false);
   }
   HIPCHK(hipStreamSynchronize(P->stream));
   HIPCHK(hipGetLastError());
@@ -705,10 +718,13 @@ template <typename T> ffth_status bicg_iter(ffth_plan* P, const Desc* d, int nb)
 
 // Iterate a plain (single precision level) scheme on descriptors d with
 // states in slots [0, nl).  The iterate must hold zero on entry.
+template <typename T> ffth_status run_cg3(ffth_plan* P, int nl);
+
 template <typename T> ffth_status run_plain(ffth_plan* P, const Desc* d, int nl) {
   const ffth_opts& o = P->opts;
   ffth_status s;
   DescSet as;
+  if (o.scheme == FFTH_CG3) return run_cg3<T>(P, nl);
   // pass 0: x = b = -Gamma0 * P_rhs, ||b||, zero right-hand-side guard
   if ((s = apply<T>(P, d, nl, XF_LS, OP_GAMMA, XI_BS, FIN_LS_FIRST)) != FFTH_OK) return s;
   if (o.scheme != FFTH_BASIC) {
@@ -737,6 +753,46 @@ template <typename T> ffth_status run_plain(ffth_plan* P, const Desc* d, int nl)
   return FFTH_OK;
 }
 
+// Three-term CG from x_0 = 0 (scheme FFTH_CG3): b = -Gamma0 * P_rhs into the
+// residual slot (r_0 = b; the zero right-hand-side guard and ||b|| from its
+// sums), the start pass, then fused iterations until the recursive residual
+// meets the tolerance.  x_k sits in slot k & 1 (f(0) or f(2)); the result is
+// copied from the last slot to the FP64 output (FP32: into slot 0, which the
+// finish widens).
+template <typename T> ffth_status run_cg3(ffth_plan* P, int nl) {
+  const ffth_opts& o = P->opts;
+  ffth_status s;
+  DescSet as;
+  if ((s = apply<T>(P, dptr(P, R_MAIN_DELTA), nl, XF_LS, OP_GAMMA, XI_BS, FIN_LS_FIRST)) != FFTH_OK) return s;
+  if ((s = read_states(P)) != FFTH_OK) return s;
+  if ((as = active_set(P, R_MAIN, 0, nl, 0)).n < 0) return FFTH_ERR_DEVICE;
+  if ((s = cg3_start<T>(P, as.d, as.n, false)) != FFTH_OK) return s;
+  if ((s = read_states(P)) != FFTH_OK) return s;
+  int it = 0;
+  while (it < o.max_iter && any_active(P, 0, nl)) {
+    const int k = std::min(o.check_every, o.max_iter - it);
+    if ((as = active_set(P, R_MAIN, 0, nl, 0)).n < 0) return FFTH_ERR_DEVICE;
+    for (int j = 0; j < k; ++j)
+      if ((s = cg3_iter<T>(P, as.d, as.n, false)) != FFTH_OK) return s;
+    it += k;
+    if ((s = read_states(P)) != FFTH_OK) return s;
+  }
+  const size_t bytes = (size_t)P->nvox * 6 * sizeof(T);
+  for (int l = 0; l < nl; ++l) {
+    const Desc& m = P->h_desc[desc_slot(P, R_MAIN, l)];
+    const SolverState& st = P->h_state[l];
+    const void* last = (st.iters & 1) ? m.x1 : m.x;
+    if (sizeof(T) == 8) {
+      double* eps = (double*)P->h_desc[desc_slot(P, R_POST, l)].x;
+      if (st.flag == FLAG_ZERO_RHS) HIPCHK(hipMemsetAsync(eps, 0, bytes, P->stream));
+      else HIPCHK(hipMemcpyAsync(eps, last, bytes, hipMemcpyDeviceToDevice, P->stream));
+    } else if (last != m.x && st.flag != FLAG_ZERO_RHS) {
+      HIPCHK(hipMemcpyAsync(m.x, last, bytes, hipMemcpyDeviceToDevice, P->stream));
+    }
+  }
+  return FFTH_OK;
+}
+
 // ---- FP32 inner solves under an FP64 defect-correction loop -----------------
 //
 // A solve is a job stepping through phases.  One round advances every job of
@@ -760,28 +816,34 @@ struct Job {
   bool fresh = false;   // inner solve entered: its three-term CG start pass is due
 };
 
-// Staging for combined descriptor arrays: 4 regions (one per phase kind) of
-// `cap` descriptors each, device copy + pinned host copy.
+// Staging for the combined descriptor arrays of one round: a device array and
+// its pinned host copy of `cap` descriptors, filled from `cursor` on.  Each
+// job is in one phase per round, so the active loads of every job of a round
+// fit in one slot each; the host copy is not rewritten before the streams the
+// round's uploads were queued on have drained.
 struct Stage {
   Desc* d;
   Desc* h;
   int cap;
+  int cursor;
 };
 
 // Append the descriptors of role r of job J whose state (slot base + l) was
 // active at the last read-back.
-int stage_append(Stage& st, int region, int count, const Job& J, Role r, int base) {
-  Desc* h = st.h + (size_t)region * st.cap;
-  for (int l = 0; l < J.nl && count < st.cap; ++l)
-    if (J.P->h_state[base + l].active) h[count++] = J.P->h_desc[desc_slot(J.P, r, l)];
-  return count;
+int stage_append(Stage& st, const Job& J, Role r, int base) {
+  int k = 0;
+  for (int l = 0; l < J.nl && st.cursor < st.cap; ++l)
+    if (J.P->h_state[base + l].active) {
+      st.h[st.cursor++] = J.P->h_desc[desc_slot(J.P, r, l)];
+      ++k;
+    }
+  return k;
 }
 
-ffth_status stage_upload(ffth_plan* dims, Stage& st, int region, int count, const Desc** out) {
-  *out = st.d + (size_t)region * st.cap;
+ffth_status stage_upload(hipStream_t stream, Stage& st, int from, int count, const Desc** out) {
+  *out = st.d + from;
   if (count > 0)
-    HIPCHK(hipMemcpyAsync(st.d + (size_t)region * st.cap, st.h + (size_t)region * st.cap, count * sizeof(Desc),
-                          hipMemcpyHostToDevice, dims->stream));
+    HIPCHK(hipMemcpyAsync(st.d + from, st.h + from, count * sizeof(Desc), hipMemcpyHostToDevice, stream));
   return FFTH_OK;
 }
 
@@ -798,10 +860,13 @@ ffth_status enter_inner(Job& J) {
   return FFTH_OK;
 }
 
-// One round for a group of mixed-precision jobs sharing grid size, material
-// kind and spectrum precision (and stream).  Every job ends the round with its
-// states read back.
-ffth_status group_round(std::vector<Job*>& jobs, Stage& st) {
+// Queue one round for a group of mixed-precision jobs sharing grid size,
+// material kind, scheme and spectrum precision, on the first job's stream:
+// the launches of every phase and the state read-back of every job.  Nothing
+// waits for the device; group_advance runs once the stream has drained.
+// *kin receives the inner iterations queued.
+ffth_status group_issue(std::vector<Job*>& jobs, Stage& st, int* kin_out) {
+  *kin_out = 0;
   if (jobs.empty()) return FFTH_OK;
   ffth_plan* dims = jobs[0]->P;
   const ffth_opts& o = dims->opts;
@@ -814,53 +879,67 @@ ffth_status group_round(std::vector<Job*>& jobs, Stage& st) {
     // one grid, material kind, precision and scheme share the tuned shapes.
     const ffth_plan* P = J->P;
     if (P->n[0] != dims->n[0] || P->n[1] != dims->n[1] || P->n[2] != dims->n[2] || P->iso != dims->iso ||
-        P->h16 != dims->h16 || P->opts.scheme != o.scheme) {
-      g_last_error = "jobs of one round differ in grid, material kind, scheme or spectrum precision";
+        P->h16 != dims->h16 || P->opts.scheme != o.scheme || P->stream != dims->stream) {
+      g_last_error = "jobs of one round differ in grid, material kind, scheme, spectrum precision or stream";
       return FFTH_ERR_INVALID;
     }
   }
-  int nA0 = 0, nA = 0, nPR = 0, nIN = 0, nFresh = 0;
+  int from[4], cnt[4] = {0, 0, 0, 0}, nFresh = 0;
   int kin = o.check_every;
-  for (Job* J : jobs) {
-    switch (J->phase) {
-      case PH_A0: nA0 = stage_append(st, 0, nA0, *J, R_MAIN, 0); break;
-      case PH_A: nA = stage_append(st, 1, nA, *J, R_MAIN_DELTA, 0); break;
-      case PH_PROJ: nPR = stage_append(st, 2, nPR, *J, R_PROJ, 0); break;
-      default: break;
-    }
+  const Role role[3] = {R_MAIN, R_MAIN_DELTA, R_PROJ};
+  for (int ph = PH_A0; ph <= PH_PROJ; ++ph) {
+    from[ph] = st.cursor;
+    for (Job* J : jobs)
+      if (J->phase == ph) cnt[ph] += stage_append(st, *J, role[ph], 0);
   }
   // inner loads: those whose solve starts this round first (they take the start pass)
+  from[3] = st.cursor;
   for (int pass = 0; pass < 2; ++pass) {
     for (Job* J : jobs) {
       if (J->phase != PH_INNER || J->fresh != (pass == 0)) continue;
-      nIN = stage_append(st, 3, nIN, *J, R_INNER, J->nl);
-      if (pass == 0) nFresh = nIN;
+      cnt[3] += stage_append(st, *J, R_INNER, J->nl);
+      if (pass == 0) nFresh = cnt[3];
       kin = std::min(kin, std::max(1, o.max_iter - J->inner_total));
     }
   }
+  // binary16 kernels read the operator output through spec2: every inner
+  // descriptor must match the launch's spectrum precision
+  if (!h16_launch_ok(st.h + from[3], cnt[3], dims->h16)) {
+    g_last_error = "inner-solve descriptors do not match the launch's spectrum precision";
+    return FFTH_ERR_INVALID;
+  }
+  hipStream_t sm = dims->stream;
   const Desc* d;
-  if ((s = stage_upload(dims, st, 0, nA0, &d)) != FFTH_OK) return s;
-  if ((s = apply<double>(dims, d, nA0, XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER)) != FFTH_OK) return s;
-  if ((s = stage_upload(dims, st, 1, nA, &d)) != FFTH_OK) return s;
-  if ((s = apply<double>(dims, d, nA, XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER_P)) != FFTH_OK) return s;
-  if ((s = stage_upload(dims, st, 2, nPR, &d)) != FFTH_OK) return s;
-  if ((s = apply<float>(dims, d, nPR, XF_C0, OP_GAMMA, XI_PROJ, FIN_PROJ)) != FFTH_OK) return s;
-  if ((s = stage_upload(dims, st, 3, nIN, &d)) != FFTH_OK) return s;
-  if (o.scheme == FFTH_CG && (s = cg3_start(dims, d, nFresh)) != FFTH_OK) return s;
+  if ((s = stage_upload(sm, st, from[0], cnt[0], &d)) != FFTH_OK) return s;
+  if ((s = apply<double>(dims, d, cnt[0], XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER)) != FFTH_OK) return s;
+  if ((s = stage_upload(sm, st, from[1], cnt[1], &d)) != FFTH_OK) return s;
+  if ((s = apply<double>(dims, d, cnt[1], XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER_P)) != FFTH_OK) return s;
+  if ((s = stage_upload(sm, st, from[2], cnt[2], &d)) != FFTH_OK) return s;
+  if ((s = apply<float>(dims, d, cnt[2], XF_C0, OP_GAMMA, XI_PROJ, FIN_PROJ)) != FFTH_OK) return s;
+  if ((s = stage_upload(sm, st, from[3], cnt[3], &d)) != FFTH_OK) return s;
+  const int nIN = cnt[3];
+  if (o.scheme == FFTH_CG && (s = cg3_start<float>(dims, d, nFresh, dims->h16)) != FFTH_OK) return s;
   for (int j = 0; j < kin && nIN > 0; ++j) {
     if (o.scheme == FFTH_BASIC) s = apply<float>(dims, d, nIN, XF_MATVEC, OP_GAMMA, XI_BS_INNER, FIN_BS);
-    else s = cg3_iter(dims, d, nIN);
+    else s = cg3_iter<float>(dims, d, nIN, dims->h16);
     if (s != FFTH_OK) return s;
   }
   for (Job* J : jobs) J->fresh = false;
   for (Job* J : jobs)
     HIPCHK(hipMemcpyAsync(J->P->h_state, J->P->d_state, J->P->L.nstate * sizeof(SolverState),
-                          hipMemcpyDeviceToHost, dims->stream));
-  HIPCHK(hipStreamSynchronize(dims->stream));
+                          hipMemcpyDeviceToHost, sm));
+  *kin_out = kin;
+  return FFTH_OK;
+}
+
+// Phase transitions of a group after its stream has drained (the states read
+// back by group_issue are current).
+ffth_status group_advance(std::vector<Job*>& jobs, int kin) {
+  ffth_status s;
   for (Job* J : jobs) prof_flush(J->P);
-  // transitions
   for (Job* J : jobs) {
     ffth_plan* P = J->P;
+    const ffth_opts& o = P->opts;
     switch (J->phase) {
       case PH_A0:
       case PH_A:
@@ -887,11 +966,15 @@ ffth_status run_mixed(ffth_plan* P, int nl) {
   Job J;
   J.P = P;
   J.nl = nl;
-  Stage st{P->d_cdesc, P->h_cdesc, P->nloads};
   std::vector<Job*> jobs{&J};
   ffth_status s;
-  while (J.phase != PH_DONE)
-    if ((s = group_round(jobs, st)) != FFTH_OK) return s;
+  while (J.phase != PH_DONE) {
+    Stage st{P->d_cdesc, P->h_cdesc, 4 * P->nloads, 0};
+    int kin = 0;
+    if ((s = group_issue(jobs, st, &kin)) != FFTH_OK) return s;
+    HIPCHK(hipStreamSynchronize(P->stream));
+    if ((s = group_advance(jobs, kin)) != FFTH_OK) return s;
+  }
   return FFTH_OK;
 }
 
@@ -920,7 +1003,20 @@ void build_solve_descs(ffth_plan* P, int nl, const double* E, double* eps, bool 
     m.st = st_main(P, l);
     m.st2 = st_inner(P, l);
     double* epsl = eps + (size_t)l * 6 * P->nvox;
-    if (o.precision == FFTH_FP64) {
+    if (o.scheme == FFTH_CG3) {
+      // x_k, r_k in slots 0, 1 (k even) or 2, 3 (k odd) of the workspace
+      if (o.precision == FFTH_FP64) {
+        m.x = f64_ptr(P, l, 0);
+        m.r = f64_ptr(P, l, 1);
+        m.x1 = f64_ptr(P, l, 2);
+        m.r1 = f64_ptr(P, l, 3);
+      } else {
+        m.x = f32_ptr(P, l, 0);
+        m.r = f32_ptr(P, l, 1);
+        m.x1 = f32_ptr(P, l, 2);
+        m.r1 = f32_ptr(P, l, 3);
+      }
+    } else if (o.precision == FFTH_FP64) {
       m.x = epsl;
       if (o.scheme == FFTH_CG) {
         m.r = f64_ptr(P, l, 0);
@@ -963,6 +1059,7 @@ void build_solve_descs(ffth_plan* P, int nl, const double* E, double* eps, bool 
       pr.r = f64_ptr(P, l, 0);
       pr.out = f32_ptr(P, l, 1);
     }
+    if (o.scheme == FFTH_CG3) md.x = m.r;   // b = -Gamma0 * P_rhs goes to the residual slot (r_0 = b)
     P->h_desc[desc_slot(P, R_MAIN_DELTA, l)] = md;
     P->h_desc[desc_slot(P, R_PROJ, l)] = pr;
     Desc in = base_desc(P, l);
@@ -1010,9 +1107,10 @@ ffth_status solve_begin(ffth_plan* P, int nl, bool keep_gscale) {
     for (int l = 0; l < nl; ++l) sts[l].gscale = P->h_state[2 * P->nloads + l].gscale;
   }
   if ((s = upload_states(P, sts, 0)) != FFTH_OK) return s;
-  // zero the iterate
+  // zero the iterate (three-term CG: the residual slot, which the first pass
+  // reads as its iterate and overwrites with b)
   for (int l = 0; l < nl; ++l) {
-    const Desc& m = P->h_desc[desc_slot(P, R_MAIN, l)];
+    const Desc& m = P->h_desc[desc_slot(P, o.scheme == FFTH_CG3 ? R_MAIN_DELTA : R_MAIN, l)];
     const size_t bytes = (size_t)P->nvox * 6 * (o.precision == FFTH_FP32 ? sizeof(float) : sizeof(double));
     HIPCHK(hipMemsetAsync(m.x, 0, bytes, P->stream));
   }
@@ -1067,6 +1165,8 @@ ffth_status solve_finish(ffth_plan* P, int nl, double* eps, ffth_result* res, do
       r.projections = m.proj;
     } else {
       r.iters = m.iters;
+      // right-hand side (+ CG: r_0 = b - A b) and one application per iteration
+      // (BiCGSTAB: two)
       const int apps = o.scheme == FFTH_BICGSTAB ? 2 * m.iters + 2 : m.iters + (o.scheme == FFTH_CG ? 2 : 1);
       r.fp64_applications = o.precision == FFTH_FP64 ? apps : 0;
     }
@@ -1171,7 +1271,7 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
     g_last_error = "reference medium needs mu0 != 0 and lambda0 + 2 mu0 != 0";
     return FFTH_ERR_INVALID;
   }
-  if (o->scheme == FFTH_CG && !(p->mu0 > 0.0 && 3.0 * p->lambda0 + 2.0 * p->mu0 > 0.0)) {
+  if ((o->scheme == FFTH_CG || o->scheme == FFTH_CG3) && !(p->mu0 > 0.0 && 3.0 * p->lambda0 + 2.0 * p->mu0 > 0.0)) {
     g_last_error = "CG needs a positive definite reference medium";
     return FFTH_ERR_INVALID;
   }
@@ -1651,6 +1751,7 @@ struct Request {
   ffth_status status = FFTH_OK;
   std::vector<ffth_result> res;
   double t_submit = 0, t_start = 0;
+  int bypassed = 0;               // admissions that passed this request while it waited
 };
 
 size_t request_bytes(const int n[3], int nph, int nl, const ffth_opts& o, size_t* ws) {
@@ -1663,13 +1764,22 @@ size_t request_bytes(const int n[3], int nph, int nl, const ffth_opts& o, size_t
 
 }  // namespace
 
+// Streams of a server: the caller's and FFTH_SERVER_STREAMS - 1 of its own.
+// Each grid size is bound to one of them (in order of first appearance), so
+// the launches of different sizes queue on different hardware queues and run
+// concurrently; one step waits for all of them once.
+constexpr int FFTH_SERVER_STREAMS = 4;
+
 struct ffth_server {
   char* arena = nullptr;
   size_t bytes = 0;
   hipStream_t stream = nullptr;
+  std::vector<hipStream_t> streams;         // [0] = the caller's; the rest created here
+  std::map<std::array<int, 3>, int> size_stream;   // grid -> index into streams
   ffth_opts opts{};
   int max_running = 0;
-  Stage stage{nullptr, nullptr, 0};
+  int max_bypass = 0;                      // admissions that may pass a waiting request
+  Stage stage{nullptr, nullptr, 0, 0};
   FreeList free_;                          // free ranges of the arena
   std::deque<Request*> waiting;
   std::vector<Request*> running;
@@ -1691,15 +1801,33 @@ void finish_request(ffth_server* S, Request* r, ffth_status st) {
   r->state = st == FFTH_ERR_CANCELLED ? 3 : 2;
 }
 
-// Admit waiting requests in arrival order while their memory fits the arena
-// and a slot is free (head-of-line order is kept).
+hipStream_t stream_for(ffth_server* S, const int n[3]) {
+  const std::array<int, 3> key{n[0], n[1], n[2]};
+  auto it = S->size_stream.find(key);
+  if (it == S->size_stream.end())
+    it = S->size_stream.emplace(key, (int)(S->size_stream.size() % S->streams.size())).first;
+  return S->streams[it->second];
+}
+
+// Admit waiting requests while a slot is free: the request of least work
+// (voxels x load cases) whose memory fits the free arena goes first, so that
+// small requests do not queue behind a large head; a request passed over
+// max_bypass times is admitted next, as soon as its memory fits, and nothing
+// passes it meanwhile (admission.h).
 ffth_status admit(ffth_server* S) {
   while (!S->waiting.empty() && (int)S->running.size() < S->max_running) {
-    Request* r = S->waiting.front();
+    std::vector<WaitInfo> q;
+    q.reserve(S->waiting.size());
+    for (const Request* w : S->waiting)
+      q.push_back({w->bytes, (double)w->n[0] * w->n[1] * w->n[2] * w->nl, w->bypassed});
+    const int k = pick_next(q, S->free_, S->max_bypass);
+    if (k < 0) break;
+    Request* r = S->waiting[k];
     size_t off;
     if (!S->free_.alloc(r->bytes, &off)) break;
-    S->waiting.pop_front();
-    const size_t stage_bytes = al((size_t)4 * S->stage.cap * sizeof(Desc));
+    for (int i = 0; i < k; ++i) S->waiting[i]->bypassed++;
+    S->waiting.erase(S->waiting.begin() + k);
+    const size_t stage_bytes = al((size_t)S->stage.cap * sizeof(Desc));
     if (off < stage_bytes || off + r->bytes > S->bytes) {   // never place over the staging area
       finish_request(S, r, FFTH_ERR_OOM);
       continue;
@@ -1708,7 +1836,8 @@ ffth_status admit(ffth_server* S) {
     r->placed = true;
     r->prob.lame = r->iso ? r->table.data() : nullptr;
     r->prob.stiffness = r->iso ? nullptr : r->table.data();
-    ffth_status st = ffth_plan_create(&r->P, &r->prob, &S->opts, r->nl, 0, S->arena + off, r->ws_bytes, S->stream);
+    ffth_status st = ffth_plan_create(&r->P, &r->prob, &S->opts, r->nl, 0, S->arena + off, r->ws_bytes,
+                                      stream_for(S, r->n));
     if (st != FFTH_OK) {
       r->P = nullptr;
       finish_request(S, r, st);
@@ -1753,8 +1882,9 @@ ffth_status ffth_server_create(ffth_server** out, void* arena, size_t arena_byte
     g_last_error = "arena must be 256-byte aligned; serving runs the mixed-precision solver";
     return FFTH_ERR_INVALID;
   }
+  // every running request has at most 6 loads, each staged once per step
   const int cap = 6 * max_running;
-  const size_t stage_bytes = al((size_t)4 * cap * sizeof(Desc));
+  const size_t stage_bytes = al((size_t)cap * sizeof(Desc));
   if (arena_bytes <= stage_bytes) {
     g_last_error = "arena too small";
     return FFTH_ERR_OOM;
@@ -1765,12 +1895,25 @@ ffth_status ffth_server_create(ffth_server** out, void* arena, size_t arena_byte
   S->stream = (hipStream_t)hip_stream;
   S->opts = *o;
   S->max_running = max_running;
+  S->max_bypass = max_running;
   S->stage.d = (Desc*)S->arena;
   S->stage.cap = cap;
-  if (!hip_ok(hipHostMalloc((void**)&S->stage.h, (size_t)4 * cap * sizeof(Desc), hipHostMallocDefault),
+  if (!hip_ok(hipHostMalloc((void**)&S->stage.h, (size_t)cap * sizeof(Desc), hipHostMallocDefault),
               "hipHostMalloc")) {
     delete S;
     return FFTH_ERR_DEVICE;
+  }
+  S->streams.push_back(S->stream);
+  for (int i = 1; i < FFTH_SERVER_STREAMS; ++i) {
+    hipStream_t st;
+    // default priority, no implicit synchronisation with the null stream
+    if (!hip_ok(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate")) {
+      for (size_t j = 1; j < S->streams.size(); ++j) (void)hipStreamDestroy(S->streams[j]);
+      (void)hipHostFree(S->stage.h);
+      delete S;
+      return FFTH_ERR_DEVICE;
+    }
+    S->streams.push_back(st);
   }
   S->free_.reset(stage_bytes, arena_bytes - stage_bytes);
   *out = S;
@@ -1805,7 +1948,7 @@ ffth_status ffth_submit(ffth_server* S, const ffth_problem* p, int32_t nloads, c
   r->E.assign(E, E + 6 * nloads);
   r->bytes = request_bytes(r->n, p->nphases, nloads, S->opts, &r->ws_bytes);
   r->t_submit = now_s();
-  if (r->bytes > S->bytes - al((size_t)4 * S->stage.cap * sizeof(Desc))) {
+  if (r->bytes > S->bytes - al((size_t)S->stage.cap * sizeof(Desc))) {
     delete r;
     g_last_error = "request larger than the whole arena";
     return FFTH_ERR_OOM;
@@ -1822,18 +1965,20 @@ ffth_status ffth_server_step(ffth_server* S, int32_t* running, int32_t* waiting)
   ffth_status st = admit(S);
   if (st != FFTH_OK) return st;
   // group running jobs by grid, material kind and spectrum precision (the
-  // launches of a group take the first job's kernels); one round per group
+  // launches of a group take the first job's kernels); every group's round is
+  // queued on its grid's stream, then the step waits for all streams once
   std::map<std::tuple<int, int, int, bool, bool>, std::vector<Job*>> groups;
   for (Request* r : S->running)
     groups[std::make_tuple(r->n[0], r->n[1], r->n[2], r->iso, r->job.P->h16)].push_back(&r->job);
-  for (auto& kv : groups) {
-    std::vector<Job*>& all = kv.second;
-    const int per = std::max(1, S->stage.cap / 6);
-    for (size_t i = 0; i < all.size(); i += per) {
-      std::vector<Job*> chunk(all.begin() + i, all.begin() + std::min(all.size(), i + per));
-      if ((st = group_round(chunk, S->stage)) != FFTH_OK) return st;
-    }
-  }
+  S->stage.cursor = 0;
+  std::vector<int> kin(groups.size(), 0);
+  size_t gi = 0;
+  for (auto& kv : groups)
+    if ((st = group_issue(kv.second, S->stage, &kin[gi++])) != FFTH_OK) return st;
+  for (hipStream_t sm : S->streams) HIPCHK(hipStreamSynchronize(sm));
+  gi = 0;
+  for (auto& kv : groups)
+    if ((st = group_advance(kv.second, kin[gi++])) != FFTH_OK) return st;
   // completed solves: volume averages, results, memory back to the arena
   std::vector<Request*> still;
   for (Request* r : S->running) {
@@ -1888,7 +2033,8 @@ ffth_status ffth_server_destroy(ffth_server* S) {
     if (r->P) (void)ffth_plan_destroy(r->P);
     delete r;
   }
-  (void)hipStreamSynchronize(S->stream);
+  for (hipStream_t sm : S->streams) (void)hipStreamSynchronize(sm);
+  for (size_t j = 1; j < S->streams.size(); ++j) (void)hipStreamDestroy(S->streams[j]);
   (void)hipHostFree(S->stage.h);
   delete S;
   return FFTH_OK;

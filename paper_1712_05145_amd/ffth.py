@@ -22,7 +22,8 @@ FFTH_OK, FFTH_ERR_INVALID, FFTH_ERR_OOM, FFTH_ERR_NOT_CONVERGED, FFTH_ERR_DIVERG
 FFTH_BASIC, FFTH_CG, FFTH_BICGSTAB = 0, 1, 2
 FFTH_FP64, FFTH_FP32, FFTH_MIXED = 0, 1, 2
 
-SCHEMES = {"basic": FFTH_BASIC, "cg": FFTH_CG, "bicgstab": FFTH_BICGSTAB}
+FFTH_CG3 = 3
+SCHEMES = {"basic": FFTH_BASIC, "cg": FFTH_CG, "bicgstab": FFTH_BICGSTAB, "cg3": FFTH_CG3}
 PRECISIONS = {"fp64": FFTH_FP64, "fp32": FFTH_FP32, "mixed": FFTH_MIXED}
 
 
@@ -140,6 +141,25 @@ def _dptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def check_field(t, device, shape, what):
+    """Raise FFTHError(FFTH_ERR_INVALID) unless t is a contiguous float64
+    tensor of exactly `shape` on `device`.  The library takes device fields as
+    bare pointers: a tensor on another device, of another type or of fewer
+    elements would make the kernels read or write outside it."""
+    import torch
+    if not isinstance(t, torch.Tensor):
+        raise FFTHError(FFTH_ERR_INVALID, f"{what}: expected a torch tensor, got {type(t).__name__}")
+    if t.device != torch.device(device):
+        raise FFTHError(FFTH_ERR_INVALID, f"{what}: tensor on {t.device}, the plan runs on {device}")
+    if t.dtype != torch.float64:
+        raise FFTHError(FFTH_ERR_INVALID, f"{what}: dtype {t.dtype}, expected torch.float64")
+    if tuple(t.shape) != tuple(shape):
+        raise FFTHError(FFTH_ERR_INVALID, f"{what}: shape {tuple(t.shape)}, expected {tuple(shape)}")
+    if not t.is_contiguous():
+        raise FFTHError(FFTH_ERR_INVALID, f"{what}: tensor is not contiguous")
+    return t
+
+
 def _darr(a):
     a = np.ascontiguousarray(a, dtype=np.float64)
     return a, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
@@ -253,7 +273,7 @@ def ffth_profile_enable(plan, on=True):
     _check(load().ffth_profile_enable(plan, 1 if on else 0), "ffth_profile_enable")
 
 
-PROFILE_CATEGORIES = 12
+PROFILE_CATEGORIES = 14
 
 
 def ffth_profile_read(plan):
@@ -286,6 +306,8 @@ class Solver:
         import torch
         self.torch = torch
         self.device = torch.device(device)
+        if self.device.type == "cuda" and self.device.index is None:
+            self.device = torch.device("cuda", torch.cuda.current_device())
         if isinstance(phase, np.ndarray):
             ph = torch.from_numpy(np.ascontiguousarray(phase.astype(np.int16, copy=False).view(np.int16)))
         else:
@@ -337,13 +359,20 @@ class Solver:
     def tile_variants(self, v):
         ffth_set_tile_variants(self.plan, v)
 
+    def _out(self, out, nl):
+        if out is None:
+            return self.field(6, nl)
+        return check_field(out, self.device, (nl, 6) + self.n, "out")
+
     def field(self, comps=6, nloads=1):
         return self.torch.empty((nloads, comps) + self.n, dtype=self.torch.float64, device=self.device)
 
     def solve_order0(self, E, out=None, check=True):
         E = np.asarray(E, dtype=np.float64).reshape(-1, 6)
         nl = E.shape[0]
-        eps = out if out is not None else self.field(6, nl)
+        if nl > self.nloads:
+            raise FFTHError(FFTH_ERR_INVALID, f"{nl} load cases, the plan holds {self.nloads}")
+        eps = self._out(out, nl)
         st, res = ffth_solve_order0(self.plan, E, _dptr(eps), nl)
         if check:
             _check(st, "ffth_solve_order0")
@@ -352,21 +381,23 @@ class Solver:
     def solve_order1(self, eps0_six, G, out=None, check=True):
         G = np.asarray(G, dtype=np.float64).reshape(-1, 18)
         nl = G.shape[0]
-        eps = out if out is not None else self.field(6, nl)
-        e0 = eps0_six.contiguous()
+        if nl > self.nloads:
+            raise FFTHError(FFTH_ERR_INVALID, f"{nl} load cases, the plan holds {self.nloads}")
+        eps = self._out(out, nl)
+        e0 = check_field(eps0_six, self.device, (6, 6) + self.n, "eps0_six")
         st, res = ffth_solve_order1(self.plan, _dptr(e0), G, _dptr(eps), nl)
         if check:
             _check(st, "ffth_solve_order1")
         return eps, res
 
     def green_apply(self, tau, precision="fp64"):
-        tau = tau.contiguous().to(self.torch.float64)
+        tau = check_field(tau, self.device, (6,) + self.n, "tau")
         eta = self.torch.empty_like(tau)
         ffth_green_apply(self.plan, _dptr(tau), _dptr(eta), PRECISIONS[precision])
         return eta
 
     def displacement(self, eps):
-        eps = eps.contiguous().to(self.torch.float64)
+        eps = check_field(eps, self.device, (6,) + self.n, "eps")
         u = self.torch.empty((3,) + self.n, dtype=self.torch.float64, device=self.device)
         ffth_displacement(self.plan, _dptr(eps), _dptr(u))
         return u
@@ -374,22 +405,28 @@ class Solver:
     def solve_order2(self, eps0_six, eps1_18, H, out=None, check=True):
         H = np.asarray(H, dtype=np.float64).reshape(-1, 54)
         nl = H.shape[0]
-        eps = out if out is not None else self.field(6, nl)
-        st, res = ffth_solve_order2(self.plan, _dptr(eps0_six.contiguous()), _dptr(eps1_18.contiguous()), H,
-                                    _dptr(eps), nl)
+        if nl > self.nloads:
+            raise FFTHError(FFTH_ERR_INVALID, f"{nl} load cases, the plan holds {self.nloads}")
+        eps = self._out(out, nl)
+        e0 = check_field(eps0_six, self.device, (6, 6) + self.n, "eps0_six")
+        e1 = check_field(eps1_18, self.device, (18, 6) + self.n, "eps1_18")
+        st, res = ffth_solve_order2(self.plan, _dptr(e0), _dptr(e1), H, _dptr(eps), nl)
         if check:
             _check(st, "ffth_solve_order2")
         return eps, res
 
     def order2_rhs(self, eps0_six, eps1_18, H):
         p = self.torch.empty((6,) + self.n, dtype=self.torch.float64, device=self.device)
-        gm = ffth_order2_rhs(self.plan, _dptr(eps0_six.contiguous()), _dptr(eps1_18.contiguous()),
+        eps0_six = check_field(eps0_six, self.device, (6, 6) + self.n, "eps0_six")
+        eps1_18 = check_field(eps1_18, self.device, (18, 6) + self.n, "eps1_18")
+        gm = ffth_order2_rhs(self.plan, _dptr(eps0_six), _dptr(eps1_18),
                              np.asarray(H, np.float64).reshape(54), _dptr(p))
         return p, gm
 
     def order1_rhs(self, eps0_six, G):
         p = self.torch.empty((6,) + self.n, dtype=self.torch.float64, device=self.device)
-        gm = ffth_order1_rhs(self.plan, _dptr(eps0_six.contiguous()), np.asarray(G, np.float64).reshape(18),
+        eps0_six = check_field(eps0_six, self.device, (6, 6) + self.n, "eps0_six")
+        gm = ffth_order1_rhs(self.plan, _dptr(eps0_six), np.asarray(G, np.float64).reshape(18),
                              _dptr(p))
         return p, gm
 

@@ -31,41 +31,58 @@ def _drain(srv, ids):
     raise AssertionError("server did not drain")
 
 
+def _alone(req):
+    from paper_1712_05145_amd.serving import Server
+    srv = Server(16 << 30, max_running=8)
+    rid = srv.submit(*req, np.eye(6))
+    out = _drain(srv, [rid])[rid]
+    srv.close()
+    return out
+
+
 def test_alone_equals_mix_and_plan_path():
-    """Request a (128^3, stiffness contrast within the binary16 limit) shares its
-    grid with a request above the limit: the server runs the two in separate
-    launch groups, and a's results are the same alone, in the mix and through
-    the plan path."""
+    """Requests that share launches give bit-identical results alone and in
+    the mix: a and b (128^3, stiffness contrast within the binary16 limit)
+    share every binary16 launch; c and e (64^3, FP32 spectrum) share every
+    launch of their group.  d shares the 128^3 grid but is above the contrast
+    limit, so the server runs it in a separate launch group; the 48^3 request
+    runs alone in its group.  a is also identical through the plan path."""
     torch = require_gpu()
     from paper_1712_05145_amd.serving import Server
     a = _req(128, 0.25, 20.0, 1)
-    others = [_req(64, 0.3, 200.0, 2), _req(48, 0.2, 10.0, 3), _req(128, 0.35, 400.0, 4), _req(64, 0.1, 5.0, 5)]
+    b = _req(128, 0.3, 12.0, 6)
+    c = _req(64, 0.3, 200.0, 2)
+    d = _req(128, 0.35, 400.0, 4)
+    e = _req(64, 0.1, 5.0, 5)
+    f = _req(48, 0.2, 10.0, 3)
     lim = ffth.SPECTRUM16_MAX_CONTRAST
-    assert ffth.ffth_stiffness_contrast(lame=a[1]) <= lim < ffth.ffth_stiffness_contrast(lame=others[2][1])
-    budget = 16 << 30
-    s1 = Server(budget, max_running=8)
-    ida = s1.submit(*a, np.eye(6))
-    alone = _drain(s1, [ida])[ida]
-    s1.close()
-    s2 = Server(budget, max_running=8)
-    ids = [s2.submit(*others[0], np.eye(6)), s2.submit(*others[1], np.eye(6))]
-    idb = s2.submit(*a, np.eye(6))
-    ids += [idb, s2.submit(*others[2], np.eye(6)), s2.submit(*others[3], np.eye(6))]
-    mixed = _drain(s2, list(ids))
+    assert ffth.ffth_stiffness_contrast(lame=a[1]) <= lim and ffth.ffth_stiffness_contrast(lame=b[1]) <= lim
+    assert ffth.ffth_stiffness_contrast(lame=d[1]) > lim
+    shared = {"a": a, "b": b, "c": c, "e": e}
+    alone = {k: _alone(r) for k, r in shared.items()}
+    s2 = Server(16 << 30, max_running=8)
+    order = [("c", c), ("f", f), ("a", a), ("d", d), ("e", e), ("b", b)]
+    ids = {k: s2.submit(*r, np.eye(6)) for k, r in order}
+    mixed = _drain(s2, list(ids.values()))
     s2.close()
-    assert alone[0] == 0 and mixed[idb][0] == 0
-    ra = np.array([r["mean_stress"] for r in alone[1]])
-    rm = np.array([r["mean_stress"] for r in mixed[idb][1]])
-    assert np.array_equal(ra, rm)                     # bit-identical alone and in the mix
-    assert [r["iters"] for r in alone[1]] == [r["iters"] for r in mixed[idb][1]]
+    for k in shared:
+        st_alone, ra = alone[k]
+        st_mix, rm = mixed[ids[k]]
+        assert st_alone == 0 and st_mix == 0, k
+        # bit-identical alone and in the mix
+        assert np.array_equal(np.array([r["mean_stress"] for r in ra]), np.array([r["mean_stress"] for r in rm])), k
+        assert [r["iters"] for r in ra] == [r["iters"] for r in rm], k
+        assert [r["fp64_applications"] for r in ra] == [r["fp64_applications"] for r in rm], k
     # and identical to the single-plan path
     sol = ffth.Solver(a[0], a[2], a[3], lame=a[1], nloads=6, precision="mixed", tol=1e-8)
     _, rp = sol.solve_order0(np.eye(6))
-    assert np.array_equal(np.array([r["mean_stress"] for r in rp]), ra)
-    for rid in ids:
-        assert mixed[rid][0] == 0
-        c = np.array([r["mean_stress"] for r in mixed[rid][1]]).T
-        assert np.abs(c - c.T).max() < 1e-6 * np.abs(c).max()
+    sol.close()
+    assert np.array_equal(np.array([r["mean_stress"] for r in rp]),
+                          np.array([r["mean_stress"] for r in alone["a"][1]]))
+    for k, rid in ids.items():
+        assert mixed[rid][0] == 0, k
+        cm = np.array([r["mean_stress"] for r in mixed[rid][1]]).T
+        assert np.abs(cm - cm.T).max() < 1e-6 * np.abs(cm).max(), k
 
 
 def test_budget_admission_cancel_and_oversize():

@@ -294,6 +294,33 @@ ffth_status ffth_poll(ffth_server *srv, uint64_t request_id, ffth_result *res);
 ffth_status ffth_cancel(ffth_server *srv, uint64_t request_id);
 ffth_status ffth_server_destroy(ffth_server *srv);
 
+/* ---- Allocation-free Green operator application ----------------------
+ * For callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation.  Computes
+ * what ffth_green_apply computes on a plan of grid n with reference medium
+ * (lambda0, mu0): eta = -Gamma0 * tau (eq. (5) and the formula below it), with
+ * the same kernels, but needs neither a plan nor a workspace: every device
+ * buffer beyond tau and eta (descriptor, state, block sums, phase ids, half
+ * spectrum) lives in one fixed array of FFTH_NOALLOC_SCRATCH_BYTES bytes in
+ * the library, one copy per GPU, held until the process ends.  The call
+ * allocates nothing: no hipMalloc, hipFree or allocating library routine.
+ *   n:       grid (as ffth_size_supported; n0 = 1 allowed), at most
+ *            FFTH_NOALLOC_MAX_VOXELS voxels, else FFTH_ERR_INVALID (the
+ *            message names the limit; nothing is queued).
+ *   tau, eta: DEVICE FP64 [6][N] (may alias); precision FFTH_FP64 or
+ *            FFTH_FP32 (input rounded to FP32, output widened back).
+ *   hip_stream: hipStream_t to queue on (NULL = default).  The call returns
+ *            once the work is queued; eta is ready when the stream reaches
+ *            that point.
+ * Every call on one GPU uses that GPU's single array, and each call
+ * rewrites it before use: calls queued on one stream are ordered and
+ * correct; calls that overlap on one GPU (different streams or threads)
+ * race on the array and give wrong results. */
+#define FFTH_NOALLOC_MAX_VOXELS 262144
+#define FFTH_NOALLOC_SCRATCH_BYTES 21497088
+ffth_status ffth_green_apply_noalloc(const int32_t n[3], double lambda0, double mu0, const double *tau,
+                                     double *eta, int32_t precision, void *hip_stream);
+
 const char *ffth_status_string(ffth_status s);
 
 /* Last HIP error text recorded by the library on this thread ("" if none). */

@@ -200,6 +200,7 @@ double stiffness_contrast(int nph, bool iso, const double* lame, const double* v
 
 }  // namespace
 
+void ffth::set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
 
 struct ffth_plan {
   int n[3];

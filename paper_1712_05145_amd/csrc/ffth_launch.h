@@ -50,4 +50,7 @@ hipError_t launch_order2_point(bool iso, int nblk, int nbatch, hipStream_t s, co
 hipError_t launch_widen(int nbatch, hipStream_t s, const Desc* d, long n);
 hipError_t launch_phase_max(hipStream_t s, const uint16_t* phase, long n, int* out);
 
+// text returned by ffth_last_error on this thread (ffth_host.hip)
+void set_last_error(const char* msg);
+
 }  // namespace ffth

@@ -110,6 +110,9 @@ SIGNATURES = [
     ("ffth_poll", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ffth_result)]),
     ("ffth_cancel", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     ("ffth_server_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("ffth_green_apply_noalloc", ctypes.c_int,
+     [ctypes.POINTER(ctypes.c_int32), ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+      ctypes.c_int32, ctypes.c_void_p]),
     ("ffth_status_string", ctypes.c_char_p, [ctypes.c_int]),
     ("ffth_last_error", ctypes.c_char_p, []),
 ]
@@ -242,6 +245,17 @@ def ffth_solve_order1(plan, eps0_ptr, G, eps_ptr, nloads):
 
 def ffth_green_apply(plan, tau_ptr, eta_ptr, precision=FFTH_FP64):
     _check(load().ffth_green_apply(plan, tau_ptr, eta_ptr, precision), "ffth_green_apply")
+
+
+NOALLOC_MAX_VOXELS = 262144   # FFTH_NOALLOC_MAX_VOXELS
+
+
+def ffth_green_apply_noalloc(n, lambda0, mu0, tau_ptr, eta_ptr, precision=FFTH_FP64, stream_ptr=None):
+    """eta = -Gamma0 * tau without a plan or workspace (the library's fixed
+    per-GPU array); queued on the stream, returns without waiting."""
+    arr = (ctypes.c_int32 * 3)(*n)
+    _check(load().ffth_green_apply_noalloc(arr, lambda0, mu0, tau_ptr, eta_ptr, precision, stream_ptr),
+           "ffth_green_apply_noalloc")
 
 
 def ffth_displacement(plan, eps_ptr, u_ptr):

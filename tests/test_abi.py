@@ -160,3 +160,26 @@ def test_spectrum16_option_range_checked_without_device():
     st = lib.ffth_plan_create(ctypes.byref(plan), ctypes.byref(pr), ctypes.byref(o), 1, 0,
                               ctypes.c_void_p(4096), 1 << 30, None)
     assert st == ffth.FFTH_ERR_INVALID
+
+
+def test_noalloc_green_rejects_before_touching_the_device():
+    """The allocation-free entry point refuses grids beyond its fixed array,
+    unsupported grids and bad arguments before queueing anything (no GPU
+    here: a call that reached the device would fail with FFTH_ERR_DEVICE)."""
+    lib = ffth.load()
+    big = (ctypes.c_int32 * 3)(64, 64, 128)          # 2 x the voxel limit
+    st = lib.ffth_green_apply_noalloc(big, 1.0, 1.0, ctypes.c_void_p(16), ctypes.c_void_p(16), ffth.FFTH_FP64,
+                                      None)
+    assert st == ffth.FFTH_ERR_INVALID
+    msg = lib.ffth_last_error().decode()
+    assert "exceeds" in msg and str(ffth.NOALLOC_MAX_VOXELS) in msg
+    odd = (ctypes.c_int32 * 3)(16, 16, 10)
+    assert lib.ffth_green_apply_noalloc(odd, 1.0, 1.0, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                        ffth.FFTH_FP64, None) == ffth.FFTH_ERR_INVALID
+    ok = (ctypes.c_int32 * 3)(16, 16, 16)
+    assert lib.ffth_green_apply_noalloc(ok, 1.0, 1.0, None, ctypes.c_void_p(16), ffth.FFTH_FP64,
+                                        None) == ffth.FFTH_ERR_INVALID
+    assert lib.ffth_green_apply_noalloc(ok, 1.0, 0.0, ctypes.c_void_p(16), ctypes.c_void_p(16), ffth.FFTH_FP64,
+                                        None) == ffth.FFTH_ERR_INVALID
+    assert lib.ffth_green_apply_noalloc(ok, 1.0, 1.0, ctypes.c_void_p(16), ctypes.c_void_p(16), 7,
+                                        None) == ffth.FFTH_ERR_INVALID

@@ -64,7 +64,8 @@ F64 = 48.0
 F32W = 24.0
 IDB = 2.0
 BYTES = {
-    # y- and z-pass of an FP64 application: spectrum read and written
+    # one y-pass (an application has two) and the z-pass of an FP64
+    # application: spectrum read and written
     "y64": 2 * F64, "z64": 2 * F64,
     # FP64 residual sweep of the defect correction (x-forward, mode LS): the
     # first sweep reads the iterate (zero) and ids and writes the spectrum;
@@ -432,7 +433,8 @@ def fp64_models(results, nvox, scheme, order1_index=6):
                 xf += B["ls_xf"] + p_read
                 xi += B["bs_xi"]
             apps += r["fp64_applications"]
-    m = {"ypass_f64": nvox * apps * B["y64"], "zpass_f64": nvox * apps * B["z64"]}
+    # two y-passes (forward, inverse) and one z-pass per application
+    m = {"ypass_f64": nvox * apps * 2 * B["y64"], "zpass_f64": nvox * apps * B["z64"]}
     if scheme in ("cg", "cg3"):
         m["xfwd_f64"] = nvox * xf
         m["xinv_f64"] = nvox * xi
@@ -463,7 +465,7 @@ def mixed_fp64_models(results, nvox, order1_index=6):
             xi += B["sweep0_xi"] + later * B["sweep_xi"]
             apps += sw
             proj += r["projections"]
-    return {"xfwd_f64": nvox * xf, "xinv_f64": nvox * xi, "ypass_f64": nvox * apps * B["y64"],
+    return {"xfwd_f64": nvox * xf, "xinv_f64": nvox * xi, "ypass_f64": nvox * apps * 2 * B["y64"],
             "zpass_f64": nvox * apps * B["z64"], "xfwd_f32": nvox * proj * B["proj_xf"],
             "xinv_f32": nvox * proj * B["proj_xi"]}
 

@@ -38,6 +38,29 @@ def test_inner_iteration_byte_model_from_its_streams():
     assert m16["xcg3"] + m16["yf"] + m16["z"] + m16["yi"] == 290.0
 
 
+F64 = COMP * 8            # one FP64 6-component field (or FP64 half spectrum)
+
+
+def test_fp64_byte_models_count_every_pass():
+    """FP64 paths: each application moves the spectrum through two y-passes and
+    one z-pass; the order-1 right-hand side adds seven applications per step
+    (six displacement transforms and theta); the three-term CG's fused pass
+    reads the spectrum, four iterates and ids and writes two iterates and the
+    spectrum."""
+    nvox = 1000
+    res = [[{"iters": 10, "fp64_applications": 11, "projections": 0}] * 7]
+    m = bench.fp64_models(res, nvox, "cg3")
+    apps = 7 * 11 + 7
+    assert m["ypass_f64"] == nvox * apps * 2 * (F64 + F64)
+    assert m["zpass_f64"] == nvox * apps * (F64 + F64)
+    assert bench.BYTES["cg3_64"] == F64 + 4 * F64 + IDS + 2 * F64 + F64
+    assert m["xcg3_f64"] == nvox * (7 * 10 * bench.BYTES["cg3_64"] - 7 * 4 * F64)
+    mm = bench.mixed_fp64_models([[{"iters": 60, "fp64_applications": 4, "projections": 2}] * 7], nvox)
+    assert mm["ypass_f64"] == nvox * (7 * 4 + 7) * 2 * (F64 + F64)
+    # projection: x-forward reads the FP64 residual and ids, writes the FP32 spectrum
+    assert mm["xfwd_f32"] == nvox * 14 * (F64 + IDS + F32)
+
+
 def _copy_tree(dst):
     root = bench.ROOT
     shutil.copytree(os.path.join(root, "paper_1712_05145_amd", "csrc"),

@@ -1448,7 +1448,8 @@ ffth_status build_rhs(ffth_plan* P, int order, int nl, const double* eps, const 
     t.st = st_post(P, l);
     t.io = gfield(P, l);     // copy-in g (3 components)
     t.nc = 3;
-    t.out = Pout[l];         // accumulate theta into P
+    t.out = Pout[l];         // accumulate theta (6 components) into P
+    t.nc_out = 6;
     P->h_desc[desc_slot(P, R_THETA, l)] = t;
   }
   if ((s = upload_descs(P)) != FFTH_OK) return s;
@@ -1467,9 +1468,6 @@ ffth_status build_rhs(ffth_plan* P, int order, int nl, const double* eps, const 
   const Desc* dt = dptr(P, R_THETA);
   if ((s = xfwd<double>(P, dt, nl, XF_COPY)) != FFTH_OK) return s;
   if ((s = yzy<double>(P, dt, nl, OP_THETA)) != FFTH_OK) return s;
-  // the accumulate pass stores 6 components
-  for (int l = 0; l < nl; ++l) P->h_desc[desc_slot(P, R_THETA, l)].nc = 6;
-  if ((s = upload_descs(P)) != FFTH_OK) return s;
   if ((s = xinv<double>(P, dt, nl, XI_ACCUM)) != FFTH_OK) return s;
   if ((s = read_states(P)) != FFTH_OK) return s;
   gmean.assign(3 * nl, 0.0);
@@ -1495,33 +1493,31 @@ ffth_status make_disp(ffth_plan* P, const double* eps0, double* out, int count) 
 ffth_status make_x1(ffth_plan* P, const double* eps0) { return make_disp(P, eps0, X1field(P), 6); }
 
 ffth_status make_x1_block(ffth_plan* P, const double* eps0, double* out, int count) {
-  // Forward + spectral operator, then inverse, one field at a time so
-  // that a single spectrum buffer suffices.
+  // Displacement transforms (forward, displacement operator, inverse) of
+  // `count` <= 6 strain fields: as many fields per launch as the plan has
+  // load spectra (each field in its own spectrum region and partial sums),
+  // all groups queued back to back without waiting for the device.
   ffth_status s;
+  const int k = std::max(1, std::min(count, P->nloads));
   for (int J = 0; J < count; ++J) {
-    Desc d = base_desc(P, 0);
-    d.part_f = part_ptr(P, 2 * P->nloads);
-    d.part_i = part_ptr(P, 2 * P->nloads + 1);
+    const int l = J % k;
+    Desc d = base_desc(P, l);
     d.st = P->d_state + 3 * P->nloads;
     d.io = (void*)(eps0 + (size_t)J * 6 * P->nvox);
     d.out = out + (size_t)J * 3 * P->nvox;
     d.nc = 6;
+    d.nc_out = 3;
     P->h_desc[util6_slot(P, J)] = d;
   }
   if ((s = upload_descs(P)) != FFTH_OK) return s;
   std::vector<SolverState> u(1, make_state(0, 1, 0, 1));
   if ((s = upload_states(P, u, 3 * P->nloads)) != FFTH_OK) return s;
-  for (int J = 0; J < count; ++J) {
-    const Desc* d = P->d_desc + util6_slot(P, J);
-    if ((s = xfwd<double>(P, d, 1, XF_COPY)) != FFTH_OK) return s;
-    if ((s = yzy<double>(P, d, 1, OP_DISP)) != FFTH_OK) return s;
-    // store 3 components: a second descriptor copy with nc = 3
-    Desc d3 = P->h_desc[util6_slot(P, J)];
-    d3.nc = 3;
-    P->h_desc[util6_slot(P, J)] = d3;
-    if ((s = upload_descs(P)) != FFTH_OK) return s;
-    if ((s = xinv<double>(P, d, 1, XI_STORE)) != FFTH_OK) return s;
-    HIPCHK(hipStreamSynchronize(P->stream));
+  for (int J0 = 0; J0 < count; J0 += k) {
+    const int nb = std::min(k, count - J0);
+    const Desc* d = P->d_desc + util6_slot(P, J0);
+    if ((s = xfwd<double>(P, d, nb, XF_COPY)) != FFTH_OK) return s;
+    if ((s = yzy<double>(P, d, nb, OP_DISP)) != FFTH_OK) return s;
+    if ((s = xinv<double>(P, d, nb, XI_STORE)) != FFTH_OK) return s;
   }
   return FFTH_OK;
 }
@@ -1645,6 +1641,7 @@ ffth_status ffth_displacement(ffth_plan* P, const double* eps, double* u) {
   d.io = (void*)eps;
   d.out = u;
   d.nc = 6;
+  d.nc_out = 3;
   P->h_desc[desc_slot(P, R_UTIL, 0)] = d;
   if ((s = upload_descs(P)) != FFTH_OK) return s;
   std::vector<SolverState> st(1, make_state(0, 1, 0, 1));
@@ -1652,8 +1649,6 @@ ffth_status ffth_displacement(ffth_plan* P, const double* eps, double* u) {
   const Desc* dd = dptr(P, R_UTIL);
   if ((s = xfwd<double>(P, dd, 1, XF_COPY)) != FFTH_OK) return s;
   if ((s = yzy<double>(P, dd, 1, OP_DISP)) != FFTH_OK) return s;
-  P->h_desc[desc_slot(P, R_UTIL, 0)].nc = 3;
-  if ((s = upload_descs(P)) != FFTH_OK) return s;
   if ((s = xinv<double>(P, dd, 1, XI_STORE)) != FFTH_OK) return s;
   HIPCHK(hipStreamSynchronize(P->stream));
   return FFTH_OK;

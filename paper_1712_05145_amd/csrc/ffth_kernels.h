@@ -449,12 +449,13 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
     }
     if (mode == XI_STORE || mode == XI_ACCUM) {
       double* op = (double*)d.out;
+      const int nco = d.nc_out ? d.nc_out : d.nc;
       double o[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) o[c] = (mode == XI_ACCUM && c < d.nc) ? op[c * nvox + vox] : 0.0;
+      for (int c = 0; c < 6; ++c) o[c] = (mode == XI_ACCUM && c < nco) ? op[c * nvox + vox] : 0.0;
 #pragma unroll
       for (int c = 0; c < 6; ++c)
-        if (c < d.nc) op[c * nvox + vox] = o[c] + (double)eta[c];
+        if (c < nco) op[c * nvox + vox] = o[c] + (double)eta[c];
     } else if (mode == XI_BS) {
       T* xp = (T*)d.x;
       T df[6];

@@ -67,10 +67,10 @@ struct Desc {
   double inv_nvox;         // 1 / voxels
   double tau_scale;        // binary16 spectrum: factor on the polarization before the x-transform
   double op_scale;         // binary16 spectrum: factor of the spectral operator (replaces 1/N)
-  int32_t nc;              // components of io (3 or 6)
+  int32_t nc;              // components of io (3 or 6) read by the copy-in x-pass
   int32_t r_f32;           // residual stored as FP32
   int32_t h16;             // the inner solve keeps its spectrum in binary16
-  int32_t pad;
+  int32_t nc_out;          // components of out written by the store / accumulate x-pass (0: nc)
 };
 
 // x-pass (forward) modes

@@ -21,6 +21,7 @@ Run:  python -m paper_1712_05145_amd.evaluation [--out FILE] [--sizes ...]
 """
 import argparse
 import json
+import os
 import time
 
 import numpy as np
@@ -98,8 +99,28 @@ def contrast_sweep(contrasts, n=64, schemes=("basic", "cg", "bicgstab")):
     return rows
 
 
+TABLE1_PATH = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "tests", "golden",
+                           "table1_time_ratios.json")
+
+
+def paper_table1(path=TABLE1_PATH):
+    """{(n, scheme): ratio} of the paper's Table 1 (Sec. 4: second- over
+    first-order time); the paper's CG version ran a BiCGSTAB routine, so its
+    column stands beside both Krylov rows here.  Empty if the file is absent."""
+    if not os.path.exists(path):
+        return {}
+    t = json.load(open(path))
+    out = {}
+    for n, bs, cg in zip(t["n"], t["basic_scheme"], t["cg_version"]):
+        out[(n, "basic")] = bs
+        out[(n, "cg")] = cg
+        out[(n, "bicgstab")] = cg
+    return out
+
+
 def write_markdown(path, grid, contrast, cmd):
     name = {"basic": "Basic Scheme", "cg": "CG", "bicgstab": "BiCGSTAB"}
+    paper = paper_table1()
     with open(path, "w") as f:
         f.write("# Sec. 4 evaluation on the GPU path: Hashin's coated inclusion, plane stress, (1, n, n) grids\n\n")
         f.write("Command (from the repository root on one MI355X):\n\n```\n" + cmd + "\n```\n\n")
@@ -109,11 +130,15 @@ def write_markdown(path, grid, contrast, cmd):
                 "clock around each problem (device synchronised), after one warm-up solve; small grids are "
                 "bound by launch latency, not by the device.\n\n")
         f.write("## Iterations and time against n\n\n")
+        f.write("The last column is the paper's Table 1 ratio for the same n (MATLAB on unstated hardware; "
+                "its CG version is a BiCGSTAB routine): context, not a target.\n\n")
         f.write("| n | scheme | order-0 iters | order-0 ms | order-1 iters | order-1 ms (incl. 3 correctors) "
-                "| ratio (Table 1) |\n|---|---|---|---|---|---|---|\n")
+                "| ratio | Table 1 |\n|---|---|---|---|---|---|---|---|\n")
         for r in grid:
+            pv = paper.get((r["n"], r["scheme"]))
             f.write(f"| {r['n']} | {name[r['scheme']]} | {r['first']['iters']} | {r['first']['seconds'] * 1e3:.2f} "
-                    f"| {r['second']['iters']} | {r['second']['seconds'] * 1e3:.2f} | {r['ratio']:.3f} |\n")
+                    f"| {r['second']['iters']} | {r['second']['seconds'] * 1e3:.2f} | {r['ratio']:.3f} "
+                    f"| {'-' if pv is None else f'{pv:.4f}'} |\n")
         f.write("\n## Iterations and time against the contrast (64 x 64)\n\n")
         f.write("Core modulus fixed, coating modulus = contrast x core, matrix modulus neutral for the pair.\n\n")
         f.write("| contrast | scheme | order-0 iters | order-0 ms | order-1 iters | order-1 ms | ratio |\n"

@@ -73,9 +73,12 @@ def test_order2_chain_on_gpu(random_case):
     torch = require_gpu()
     print("case order2 chain", flush=True)
     phase, lame, lam0, mu0, prob, corr, sols, means = random_case
-    s0 = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, tol=1e-11)
+    # the order-2 right-hand side is built from the GPU's own order-0 and
+    # order-1 fields, whose errors (about the conditioning times their
+    # residual) carry into it: they are solved one decade tighter
+    s0 = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, tol=1e-12)
     eps0, _ = s0.solve_order0(np.eye(6))
-    s1 = ffth.Solver(phase, lam0, mu0, lame=lame, order=1, nloads=18, tol=1e-11)
+    s1 = ffth.Solver(phase, lam0, mu0, lame=lame, order=1, nloads=18, tol=1e-12)
     eps1, r1 = s1.solve_order1(eps0, np.eye(18))
     for k in range(18):
         assert rel_l2(eps1[k].cpu().numpy(), voigt6(sols[k])) < 1e-6
@@ -85,7 +88,7 @@ def test_order2_chain_on_gpu(random_case):
     eref, info = H.solve_order2(prob, corr, sols, hess, "cg", tol=1e-13)
     s2 = ffth.Solver(phase, lam0, mu0, lame=lame, order=2, nloads=1, tol=1e-10)
     eps3, res = s2.solve_order2(eps0, eps1, hess.reshape(1, 54))
-    assert rel_l2(eps3[0].cpu().numpy(), voigt6(eref)) < 1e-5
+    assert rel_l2(eps3[0].cpu().numpy(), voigt6(eref)) < 1e-6
 
 
 def test_order2_homogeneous_zero():

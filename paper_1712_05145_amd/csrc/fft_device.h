@@ -24,29 +24,39 @@ template <int DIR, typename T> __device__ __forceinline__ C2<T> mul_i(C2<T> a) {
 }
 
 // ---------------------------------------------------------------------------
-// Compile-time factorisation of a transform length into radices 16,8,4,2,3,5.
+// Compile-time factorisation of a transform length into the radices 16, 8,
+// 4, 2, 3, 5.  A radix plan is the order in which the radices are preferred:
+// each stage takes the first preferred radix that divides what is left.
+//   plan 0: 16, 8, 4, 2, 3, 5   (fewest stages: 256 = 16 x 16)
+//   plan 1:  4, 2, 3, 5, 8, 16  (small butterflies: 256 = 4 x 4 x 4 x 4)
+//   plan 2:  8, 4, 2, 3, 5, 16  (256 = 8 x 8 x 4)
+// The run-time tuner times the plans (with the default tile shape) beside the
+// tile shapes of every pass.
 // ---------------------------------------------------------------------------
-constexpr int fac_count(int n) {
+constexpr int NPLAN = 3;
+constexpr int plan_radix(int plan, int i) {
+  constexpr int rs[NPLAN][6] = {{16, 8, 4, 2, 3, 5}, {4, 2, 3, 5, 8, 16}, {8, 4, 2, 3, 5, 16}};
+  return rs[plan][i];
+}
+constexpr int fac_count(int n, int plan = 0) {
   int c = 0;
-  const int rs[6] = {16, 8, 4, 2, 3, 5};
   for (int i = 0; i < 6; ++i)
-    while (n > 1 && n % rs[i] == 0) { n /= rs[i]; ++c; }
+    while (n > 1 && n % plan_radix(plan, i) == 0) { n /= plan_radix(plan, i); ++c; }
   return n == 1 ? c : -1;
 }
-constexpr int fac_radix(int n, int s) {
-  const int rs[6] = {16, 8, 4, 2, 3, 5};
+constexpr int fac_radix(int n, int s, int plan = 0) {
   int c = 0;
   for (int i = 0; i < 6; ++i)
-    while (n > 1 && n % rs[i] == 0) {
-      if (c == s) return rs[i];
-      n /= rs[i];
+    while (n > 1 && n % plan_radix(plan, i) == 0) {
+      if (c == s) return plan_radix(plan, i);
+      n /= plan_radix(plan, i);
       ++c;
     }
   return 1;
 }
-constexpr int fac_prefix(int n, int s) {  // product of radices before stage s
+constexpr int fac_prefix(int n, int s, int plan = 0) {  // product of radices before stage s
   int p = 1;
-  for (int i = 0; i < s; ++i) p *= fac_radix(n, i);
+  for (int i = 0; i < s; ++i) p *= fac_radix(n, i, plan);
   return p;
 }
 
@@ -229,11 +239,12 @@ template <typename T, int G> __device__ __forceinline__ void hstore_g(H2* p, con
 
 // One Stockham stage.  Work items are (group of V adjacent sequences, butterfly).
 // V = 2 requires FFAST layouts with sequence stride FS = 1 (adjacent sequences).
-template <typename T, int N, int S, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR, int V>
+template <typename T, int N, int S, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR, int V,
+          int PLAN = 0>
 __device__ __forceinline__ void fft_stage(C2<T>* buf, const C2<T>* tw) {
   static_assert(V == 1 || (FFAST && FS == 1 && NFFT % V == 0 && ES % V == 0), "vector width needs adjacent sequences");
-  constexpr int R = fac_radix(N, S);
-  constexpr int NS = fac_prefix(N, S);
+  constexpr int R = fac_radix(N, S, PLAN);
+  constexpr int NS = fac_prefix(N, S, PLAN);
   constexpr int NB = N / R;
   constexpr int NG = NFFT / V;
   constexpr int ITEMS = NG * NB;
@@ -285,19 +296,21 @@ __device__ __forceinline__ void fft_stage(C2<T>* buf, const C2<T>* tw) {
   __syncthreads();
 }
 
-template <typename T, int N, int S, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR, int V>
+template <typename T, int N, int S, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR, int V,
+          int PLAN>
 __device__ __forceinline__ void fft_stages(C2<T>* buf, const C2<T>* tw) {
-  if constexpr (S < fac_count(N)) {
-    fft_stage<T, N, S, NFFT, NT, ES, FS, FFAST, PADDED, DIR, V>(buf, tw);
-    fft_stages<T, N, S + 1, NFFT, NT, ES, FS, FFAST, PADDED, DIR, V>(buf, tw);
+  if constexpr (S < fac_count(N, PLAN)) {
+    fft_stage<T, N, S, NFFT, NT, ES, FS, FFAST, PADDED, DIR, V, PLAN>(buf, tw);
+    fft_stages<T, N, S + 1, NFFT, NT, ES, FS, FFAST, PADDED, DIR, V, PLAN>(buf, tw);
   }
 }
 
 // Caller must __syncthreads() before (data written) - the stages end with a barrier.
-template <typename T, int N, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR, int V = 1>
+template <typename T, int N, int NFFT, int NT, int ES, int FS, bool FFAST, bool PADDED, int DIR, int V = 1,
+          int PLAN = 0>
 __device__ __forceinline__ void lds_fft(C2<T>* buf, const C2<T>* tw) {
-  static_assert(fac_count(N) > 0, "unsupported FFT length");
-  fft_stages<T, N, 0, NFFT, NT, ES, FS, FFAST, PADDED, DIR, V>(buf, tw);
+  static_assert(fac_count(N, PLAN) > 0, "unsupported FFT length");
+  fft_stages<T, N, 0, NFFT, NT, ES, FS, FFAST, PADDED, DIR, V, PLAN>(buf, tw);
 }
 
 // ---------------------------------------------------------------------------

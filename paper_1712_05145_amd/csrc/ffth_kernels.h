@@ -63,7 +63,8 @@ template <typename T> constexpr int z_cols(int n) {
 // default is often one row, variant 1 is then two rows with 512 threads).
 // The z-pass takes twice the columns (1),
 // four times with 512 threads (2) or three times with 512 threads (3): rows
-// of >= 144 contiguous bytes in FP32.
+// of >= 144 contiguous bytes in FP32.  Variants 4 and 5 keep the default
+// tile and change the radix plan of the transform (fft_device.h).
 template <typename T> constexpr int lds_cap_rows(int n) {          // x-pass rows within 96 KB
   int r = 98304 / (3 * (n + n / 16) * (int)(2 * sizeof(T)));
   return r < 1 ? 1 : pow2_floor(r);
@@ -88,7 +89,9 @@ template <typename T> constexpr int y_cols_v(int n, int v) {
   return c;
 }
 template <typename T> constexpr int x_threads_v(int, int v) { return v == 3 ? 64 : NT; }
-template <typename T> constexpr int z_threads_v(int, int v) { return v >= 2 ? 512 : NT; }
+template <typename T> constexpr int z_threads_v(int, int v) { return v == 2 || v == 3 ? 512 : NT; }
+// variants 4 and 5: the default tile shape (variant 0) with radix plans 1 and 2
+constexpr int plan_of(int v) { return v >= 4 ? v - 3 : 0; }
 template <typename T> constexpr int xi_threads_v(int n, int v) { return xi_wide_v<T>(n, v) ? 512 : x_threads_v<T>(n, v); }
 template <typename T> constexpr int y_threads_v(int n, int v) {
   return v == 1 ? (y_threads<T>(n) == 512 ? 256 : 512) : v == 2 ? 256 : y_threads<T>(n);
@@ -235,7 +238,7 @@ __device__ __forceinline__ void load_rows_c2r(const S* spec, C2<T>* z, long row0
   }
 }
 
-template <typename T, int N2, bool ISO, int ROWS = x_rows<T>(N2), int NTB = NT, typename S = C2<T>>
+template <typename T, int N2, bool ISO, int ROWS = x_rows<T>(N2), int NTB = NT, typename S = C2<T>, int PLAN = 0>
 __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, int mode, long rows_total,
                                               long nvox) {
   constexpr int RS = N2 + N2 / 16;
@@ -409,7 +412,7 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
     for (int q = 0; q < 3; ++q) z[(rr * 3 + q) * RS + padx<true>(i2)] = C2<T>{tau[2 * q], tau[2 * q + 1]};
   }
   __syncthreads();
-  lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, -1>(z, tw);
+  lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, -1, 1, PLAN>(z, tw);
 
   store_rows_r2c<T, N2, ROWS, NTB, S>((S*)d.spec, z, row0, rows_total);
   double sums[3] = {acc0, acc1, acc2};
@@ -419,7 +422,7 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
 // ---------------------------------------------------------------------------
 // x-pass, inverse: complex-to-real FFT along axis 2 + update + reductions.
 // ---------------------------------------------------------------------------
-template <typename T, int N2, bool ISO, int ROWS = xi_rows<T>(N2), int NTB = NT>
+template <typename T, int N2, bool ISO, int ROWS = xi_rows<T>(N2), int NTB = NT, int PLAN = 0>
 __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, int mode, long rows_total, long nvox) {
   constexpr int RS = N2 + N2 / 16;
   constexpr int H = N2 / 2;
@@ -431,7 +434,7 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
   const long row0 = (long)blockIdx.x * ROWS;
   load_rows_c2r<T, N2, ROWS, NTB>((const C2<T>*)d.spec, z, row0, rows_total);
   __syncthreads();
-  lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, +1>(z, tw);
+  lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, +1, 1, PLAN>(z, tw);
 
   const T alpha = (T)d.st->alpha;
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0, acc4 = 0.0;
@@ -591,7 +594,7 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
 // (C - C0) r_{k+1}, written back over the block's own spectrum rows.
 // Iterates ping-pong between two slots: r_k, x_k sit in slot (k & 1).
 // ---------------------------------------------------------------------------
-template <typename T, int N2, bool ISO, int ROWS = xi_rows<T>(N2), int NTB = NT, typename S = C2<T>>
+template <typename T, int N2, bool ISO, int ROWS = xi_rows<T>(N2), int NTB = NT, typename S = C2<T>, int PLAN = 0>
 __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, long rows_total, long nvox) {
   constexpr int RS = N2 + N2 / 16;
   __shared__ C2<T> z[ROWS * 3 * RS];
@@ -605,7 +608,7 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
   S* spec = (S*)d.spec;
   load_rows_c2r<T, N2, ROWS, NTB>((const C2<T>*)(FULL ? d.spec : d.spec2), z, row0, rows_total);
   __syncthreads();
-  lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, +1>(z, tw);
+  lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, +1, 1, PLAN>(z, tw);
 
   const int it = d.st->iters;
   const bool first = d.st->first != 0;
@@ -681,7 +684,7 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
     for (int q = 0; q < 3; ++q) z[(rr * 3 + q) * RS + padx<true>(i2)] = C2<T>{tau[2 * q], tau[2 * q + 1]};
   }
   __syncthreads();
-  lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, -1>(z, tw);
+  lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, -1, 1, PLAN>(z, tw);
   store_rows_r2c<T, N2, ROWS, NTB, S>(spec, z, row0, rows_total);
   double sums[3] = {acc0, acc1, acc2};
   block_sums<3, NTB>(sums, d.part_i + blockIdx.x, gridDim.x);
@@ -753,7 +756,7 @@ __device__ __forceinline__ void y_h2_store(H2* base, int ncols, int c0, const C2
   }
 }
 
-template <typename T, int N1, int CW, int NTB, int DIR, int V, typename S>
+template <typename T, int N1, int CW, int NTB, int DIR, int V, typename S, int PLAN>
 __device__ __forceinline__ void ypass_body(S* base, int ncols, int c0, C2<T>* buf, const C2<T>* tw) {
   constexpr bool FULL = std::is_same<S, C2<T>>::value;
   static_assert(FULL || V == 1, "binary16 storage keeps one sequence per LDS slot");
@@ -769,7 +772,7 @@ __device__ __forceinline__ void ypass_body(S* base, int ncols, int c0, C2<T>* bu
     else y_tile_load<T, N1, CW, NTB, 1>(base, ncols, c0, buf);
   }
   __syncthreads();
-  lds_fft<T, N1, CW, NTB, CW, 1, true, false, DIR, V>(buf, tw);
+  lds_fft<T, N1, CW, NTB, CW, 1, true, false, DIR, V, PLAN>(buf, tw);
   if constexpr (FULL) {
     for (int v = threadIdx.x; v < N1 * CW / GF; v += NTB) {
       const int i1 = v / (CW / GF), col = (v % (CW / GF)) * GF;
@@ -789,7 +792,7 @@ __device__ __forceinline__ void ypass_body(S* base, int ncols, int c0, C2<T>* bu
 }
 
 template <typename T, int N1, int CW = y_cols<T>(N1), int NTB = y_threads<T>(N1), bool REMAP = true,
-          int V = vec_width<T>(), typename S = C2<T>>
+          int V = vec_width<T>(), typename S = C2<T>, int PLAN = 0>
 __global__ __launch_bounds__(NTB) void k_ypass(const Desc* __restrict__ descs, int dir, int ncols, int ntiles) {
   __shared__ __attribute__((aligned(16))) C2<T> buf[N1 * CW];
   __shared__ C2<T> tw[N1];
@@ -803,8 +806,8 @@ __global__ __launch_bounds__(NTB) void k_ypass(const Desc* __restrict__ descs, i
   // y-transform runs in FP32 on the copy the spectral operator wrote
   const bool alt = std::is_same<S, C2<T>>::value && d.spec2 != nullptr && dir > 0;
   S* base = (S*)(alt ? d.spec2 : d.spec) + i0 * N1 * (long)ncols + c0;
-  if (dir < 0) ypass_body<T, N1, CW, NTB, -1, V, S>(base, ncols, c0, buf, tw);
-  else ypass_body<T, N1, CW, NTB, +1, V, S>(base, ncols, c0, buf, tw);
+  if (dir < 0) ypass_body<T, N1, CW, NTB, -1, V, S, PLAN>(base, ncols, c0, buf, tw);
+  else ypass_body<T, N1, CW, NTB, +1, V, S, PLAN>(base, ncols, c0, buf, tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -879,7 +882,7 @@ __device__ __forceinline__ void spectral_op(int op, T (&in)[6][2], T (&out)[6][2
 }
 
 template <typename T, int N0, int TK = z_cols<T>(N0), int NTB = NT, bool REMAP = true, int V = vec_width<T>(),
-          typename S = C2<T>>
+          typename S = C2<T>, int PLAN = 0>
 __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, int op, int n1, int h, double scale) {
   constexpr int W = TK * 6;
   __shared__ __attribute__((aligned(16))) C2<T> buf[N0 * W];
@@ -934,7 +937,7 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
     }
   }
   __syncthreads();
-  if constexpr (N0 > 1) lds_fft<T, N0, W, NTB, W, 1, true, false, -1, V>(buf, tw);
+  if constexpr (N0 > 1) lds_fft<T, N0, W, NTB, W, 1, true, false, -1, V, PLAN>(buf, tw);
   for (int v = threadIdx.x; v < N0 * TK; v += NTB) {
     const int k0 = v / TK, col = v % TK;
     const long m = m0 + col;
@@ -970,7 +973,7 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
     }
   }
   __syncthreads();
-  if constexpr (N0 > 1) lds_fft<T, N0, W, NTB, W, 1, true, false, +1, V>(buf, tw);
+  if constexpr (N0 > 1) lds_fft<T, N0, W, NTB, W, 1, true, false, +1, V, PLAN>(buf, tw);
   for (int v = threadIdx.x; v < N0 * W / GZ; v += NTB) {
     const int i0 = v / (W / GZ), w = (v % (W / GZ)) * GZ;
     if (m0 + w / 6 < M) {

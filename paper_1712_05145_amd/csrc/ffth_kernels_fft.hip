@@ -44,31 +44,36 @@ template <typename T> using Full = C2<T>;
 template <typename T, int N, int V, typename S = C2<T>>
 static void xfwd_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox) {
   constexpr int RW = ffth::xf_rows_v<T>(N, V), TB = ffth::x_threads_v<T>(N, V);
-  if (iso) hipLaunchKernelGGL((k_xfwd<T, N, true, RW, TB, S>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
-  else hipLaunchKernelGGL((k_xfwd<T, N, false, RW, TB, S>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
+  constexpr int PL = ffth::plan_of(V);
+  if (iso) hipLaunchKernelGGL((k_xfwd<T, N, true, RW, TB, S, PL>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
+  else hipLaunchKernelGGL((k_xfwd<T, N, false, RW, TB, S, PL>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
 }
 template <typename T, int N, int V, typename S = C2<T>>
 static void xinv_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, int mode, long rows, long nvox) {
   constexpr int RW = ffth::xi_rows_v<T>(N, V), TB = ffth::xi_threads_v<T>(N, V);
-  if (iso) hipLaunchKernelGGL((k_xinv<T, N, true, RW, TB>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
-  else hipLaunchKernelGGL((k_xinv<T, N, false, RW, TB>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
+  constexpr int PL = ffth::plan_of(V);
+  if (iso) hipLaunchKernelGGL((k_xinv<T, N, true, RW, TB, PL>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
+  else hipLaunchKernelGGL((k_xinv<T, N, false, RW, TB, PL>), grid, dim3(TB), 0, s, d, mode, rows, nvox);
 }
 template <typename T, int N, int V, typename S = C2<T>>
 static void xcg3_v(bool iso, dim3 grid, hipStream_t s, const Desc* d, long rows, long nvox) {
   constexpr int RW = ffth::xi_rows_v<T>(N, V), TB = ffth::xi_threads_v<T>(N, V);
-  if (iso) hipLaunchKernelGGL((k_xcg3<T, N, true, RW, TB, S>), grid, dim3(TB), 0, s, d, rows, nvox);
-  else hipLaunchKernelGGL((k_xcg3<T, N, false, RW, TB, S>), grid, dim3(TB), 0, s, d, rows, nvox);
+  constexpr int PL = ffth::plan_of(V);
+  if (iso) hipLaunchKernelGGL((k_xcg3<T, N, true, RW, TB, S, PL>), grid, dim3(TB), 0, s, d, rows, nvox);
+  else hipLaunchKernelGGL((k_xcg3<T, N, false, RW, TB, S, PL>), grid, dim3(TB), 0, s, d, rows, nvox);
 }
 template <typename T, int N, int V, typename S = C2<T>>
 static void ypass_v(dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols, int ntiles) {
   constexpr int CW = ffth::y_cols_v<T>(N, V);
   constexpr int TB = ffth::y_threads_v<T>(N, V);
-  hipLaunchKernelGGL((k_ypass<T, N, CW, TB, true, 1, S>), grid, dim3(TB), 0, s, d, dir, ncols, ntiles);
+  hipLaunchKernelGGL((k_ypass<T, N, CW, TB, true, 1, S, ffth::plan_of(V)>), grid, dim3(TB), 0, s, d, dir, ncols,
+                     ntiles);
 }
 template <typename T, int N, int V, typename S = C2<T>>
 static void zpass_v(dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h, double scale) {
   constexpr int TK = ffth::z_cols_v<T>(N, V), TB = ffth::z_threads_v<T>(N, V);
-  hipLaunchKernelGGL((k_zpass<T, N, TK, TB, true, 1, S>), grid, dim3(TB), 0, s, d, op, n1, h, scale);
+  hipLaunchKernelGGL((k_zpass<T, N, TK, TB, true, 1, S, ffth::plan_of(V)>), grid, dim3(TB), 0, s, d, op, n1, h,
+                     scale);
 }
 
 #define FFTH_VARIANTS_S(F, N, S, ...)        \
@@ -76,6 +81,8 @@ static void zpass_v(dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int
     case 1: F<T, N, 1, S>(__VA_ARGS__); break; \
     case 2: F<T, N, 2, S>(__VA_ARGS__); break; \
     case 3: F<T, N, 3, S>(__VA_ARGS__); break; \
+    case 4: F<T, N, 4, S>(__VA_ARGS__); break; \
+    case 5: F<T, N, 5, S>(__VA_ARGS__); break; \
     default: F<T, N, 0, S>(__VA_ARGS__);     \
   }
 #define FFTH_VARIANTS(F, N, ...) FFTH_VARIANTS_S(F, N, C2<T>, __VA_ARGS__)

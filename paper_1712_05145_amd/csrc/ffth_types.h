@@ -89,6 +89,6 @@ enum : int32_t {
 };
 
 constexpr int NRED = 8;   // doubles per block in the partial-sum arrays
-constexpr int NVAR = 4;   // compiled tile shapes per pass (autotuner candidates)
+constexpr int NVAR = 6;   // compiled tile shapes / radix plans per pass (autotuner candidates)
 
 }  // namespace ffth

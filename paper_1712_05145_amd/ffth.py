@@ -183,6 +183,11 @@ def make_opts(scheme="cg", precision="mixed", tol=1e-8, max_iter=20000, inner_to
     return o
 
 
+# compiled candidates per pass: tile shapes 0-3, radix plans 1 and 2 on the
+# default tile (4, 5)
+TILE_VARIANTS = 6
+
+
 def ffth_tile_variants(plan):
     out = (ctypes.c_int32 * 8)()
     _check(load().ffth_tile_variants(plan, out), "ffth_tile_variants")

@@ -30,7 +30,7 @@ def _ceff_ok(c_gpu, c_ref, tol=1e-7):
     return np.all(np.abs(c_gpu - c_ref) <= tol * d)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 def test_cg3_fp64_order0_every_tile(sphere16, variant):
     torch = require_gpu()
     print("case cg3 fp64 variant", variant, flush=True)

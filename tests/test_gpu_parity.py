@@ -297,7 +297,7 @@ VARIANT_SHAPES = [(12, 24, 8), (64, 48, 32), (32, 128, 24), (24, 32, 128), (256,
                   (16, 8, 256)]
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("shape", VARIANT_SHAPES)
 def test_every_tile_variant_green_parity(variant, shape):
     """Each compiled tile shape of every pass gives the oracle's Gamma0 * tau."""
@@ -318,11 +318,11 @@ def test_tile_variant_out_of_range_rejected():
     torch = require_gpu()
     s = _uniform_solver(torch, (8, 8, 8))
     with pytest.raises(ffth.FFTHError):
-        s.tile_variants = [0, 0, 4, 0, 0, 0, 0, 0]
+        s.tile_variants = [0, 0, 6, 0, 0, 0, 0, 0]
     assert s.tile_variants == [0] * 8
 
 
-@pytest.mark.parametrize("variant", [1, 2, 3])
+@pytest.mark.parametrize("variant", [1, 2, 3, 4, 5])
 @pytest.mark.parametrize("scheme", ["cg", "basic"])
 def test_every_tile_variant_solve_parity(sphere16_oracle, variant, scheme):
     """Mixed solves with every pass on a non-default tile shape (all fused
@@ -354,7 +354,7 @@ def test_autotuned_plan_matches_default_tiles():
         s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, precision="mixed", tol=1e-9, autotune=tune)
         v = s.tile_variants
         print("variants", tune, v, flush=True)
-        assert len(v) == 8 and all(0 <= x < 4 for x in v)
+        assert len(v) == 8 and all(0 <= x < ffth.TILE_VARIANTS for x in v)
         if not tune:
             assert v == [0] * 8
         _, res = s.solve_order0(np.eye(6))

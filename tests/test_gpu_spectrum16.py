@@ -30,7 +30,7 @@ def sphere16():
     return phase, lame, lam0, mu0, ceff, corr
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
 def test_forced_spectrum16_order0_parity_every_tile(sphere16, variant):
     """Six unit loads in one batched call, every tile shape of every pass."""
     torch = require_gpu()

@@ -498,6 +498,8 @@ def main():
     ap.add_argument("--fibres-n", type=int, default=512)
     ap.add_argument("--serve-count", type=int, default=512)
     ap.add_argument("--serve-rates", default="40,20", help="request rates (per second) of the serving streams")
+    ap.add_argument("--only-serve", action="store_true",
+                    help="run the serving measurement alone and print its results (diagnostics, e.g. under a trace)")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile shapes")
     ap.add_argument("--no-spectrum16", action="store_true", help="keep the inner solve's spectrum in FP32")
     args = ap.parse_args()
@@ -515,6 +517,10 @@ def main():
     if not torch.cuda.is_available():
         raise SystemExit("bench.py needs a GPU")
     dev = torch.device("cuda:0")
+    if args.only_serve:
+        print(json.dumps({"serving": [serving_run(args.serve_count, float(r), dev)
+                                      for r in args.serve_rates.split(",")]}), flush=True)
+        return
     t = time.perf_counter()
     phase, lame = M.voronoi_polycrystal(args.n, args.grains, args.seed)
     lam0, mu0 = M.midpoint_reference(lame)

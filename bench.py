@@ -33,29 +33,33 @@ HBM_PEAK_GBS = 8000.0
 # 2-byte phase ids; the half spectrum is 6 x n/2 complex = 24 B per voxel in
 # FP32, 12 B in binary16):
 #   y-pass / z-pass        spectrum read and written                 24+24
-#   fused three-term CG    spectrum, r_k, x_k, r_k-1, x_k-1, phase read;
-#   x-pass                 r_k+1, x_k+1, spectrum written            24*5+2+24*3
+#   fused three-term CG    spectrum, r_k, r_k-1, phase read; r_k+1
+#   x-pass                 and the spectrum written; on odd iterations
+#                          also the pair x_k-1, x_k-2 read and x_k+1, x_k
+#                          written (48 B a voxel on average)        24*3+2+24*2 + 48
 #   start pass of a solve  r_0, phase read; spectrum written          24+2+24
 # With the binary16 forward spectrum of the inner solve, every write of the
 # spectrum before the spectral operator and every read of it up to there is
-# 12 B: forward y-pass 12+12, z-pass 12+24, fused pass 24*5+2+24*2+12, start
-# pass 24+2+12; the inverse y-pass (24+24) and the projection passes stay FP32.
-# The first iteration of each inner solve reads neither x_k nor r_k-1, x_k-1
-# (x_0 = 0, omega = 1) and the second does not read x_k-1: per started solve
-# the fused kernel moves 72 + 24 B/voxel less than a full iteration.  The
-# model subtracts both for every start (a lower bound on the bytes moved when
-# a solve stops after one iteration).  The FP32 x-forward / x-inverse
-# categories hold the projection passes only and are reported without a model.
+# 12 B: forward y-pass 12+12, z-pass 12+24, fused pass 24*3+2+24+12 + 48,
+# start pass 24+2+12; the inverse y-pass (24+24) and the projection passes
+# stay FP32.  The first iteration of a solve reads no r_k-1 (24 B) and the
+# second reads no x pair (x_0 = 0); a solve of K iterations moves 48 or 96 B
+# per voxel less x traffic than K times the average: the model subtracts
+# 24 + 96 for every start (a lower bound on the bytes moved).  A solve that
+# ends after an even iteration forms its last x in a separate finish kernel
+# (pointwise category).  The FP32 x-forward / x-inverse categories hold the
+# projection passes only.
 ALG_CATEGORIES = ("ypass_f32", "zpass_f32", "xcg3_f32", "cg3start_f32")
-XCG3_START_SAVING = 96.0
+XCG3_START_SAVING = 120.0
 
 
 def alg_bytes_per_voxel(h16):
-    """Bytes per voxel of (forward y, inverse y, z, fused CG pass, start pass)
-    in the inner solve; projection passes move 48 B in each y- and z-pass."""
+    """Bytes per voxel of (forward y, inverse y, z, fused CG pass averaged over
+    an even and an odd iteration, start pass) in the inner solve; projection
+    passes move 48 B in each y- and z-pass."""
     if h16:
-        return {"yf": 24.0, "yi": 48.0, "z": 36.0, "xcg3": 182.0, "start": 38.0}
-    return {"yf": 48.0, "yi": 48.0, "z": 48.0, "xcg3": 194.0, "start": 50.0}
+        return {"yf": 24.0, "yi": 48.0, "z": 36.0, "xcg3": 158.0, "start": 38.0}
+    return {"yf": 48.0, "yi": 48.0, "z": 48.0, "xcg3": 170.0, "start": 50.0}
 
 
 # FP64 words are 8 B: a 6-component FP64 field or FP64 half spectrum is 48 B
@@ -86,10 +90,13 @@ BYTES = {
     # written; x-inverse: spectrum and x read, x written) and r_0 = b - A b
     # (x-forward the same; x-inverse: spectrum, x read, r written)
     "ls_xf": IDB + F64 + F64, "bs_xi": F64 + F64 + F64, "resid_xi": F64 + F64 + F64,
-    # three-term CG in FP64: fused pass (spectrum, four iterates, ids read;
-    # two iterates and the spectrum written), start pass, and the first two
-    # iterations' skipped reads (three iterates, then one)
-    "cg3_64": F64 + 4 * F64 + IDB + 3 * F64, "cg3s_64": F64 + IDB + F64, "cg3_64_saving": 4 * F64,
+    # three-term CG in FP64: fused pass (spectrum, r_k, r_k-1, ids read; r_k+1
+    # and the spectrum written; the x pair read and written on odd iterations,
+    # 2 x 48 B a voxel on average), start pass, and per started solve the
+    # lower-bound saving of the model (no r_k-1 in the first iteration, at
+    # most one x pair less than the average)
+    "cg3_64": F64 + 2 * F64 + IDB + F64 + F64 + 2 * F64, "cg3s_64": F64 + IDB + F64,
+    "cg3_64_saving": F64 + 4 * F64,
 }
 
 

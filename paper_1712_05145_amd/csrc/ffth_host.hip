@@ -585,12 +585,13 @@ ffth_status autotune(ffth_plan* P) {
     }
   }
   ffth_status s;
-  // steady-state iterations (every field of the fused CG pass is read), and
-  // launches carrying all of the plan's loads, each on its own workspace, as
-  // the solve's launches do
+  // steady-state iterations (the fused CG pass in an odd iteration, which
+  // reads and writes the x pair beside the residuals), and launches carrying
+  // all of the plan's loads, each on its own workspace, as the solve's
+  // launches do
   SolverState us = make_state(0, 1, 0, 1);
   us.first = 0;
-  us.iters = 2;
+  us.iters = 3;
   std::vector<SolverState> u(1, us);
   if ((s = upload_states(P, u, 3 * P->nloads)) != FFTH_OK) return s;
   const Desc* dd = dptr(P, R_UTIL);
@@ -599,7 +600,7 @@ ffth_status autotune(ffth_plan* P) {
   if (o.precision != FFTH_FP64) {   // FP32 passes: the inner iteration (or the plain FP32 solve)
     int xf = XF_LS, xi = XI_BS;
     bool fused = false;
-    if ((mixed && P->L.nf32 == 4) || o.scheme == FFTH_CG3) {   // three-term CG (inner) solve
+    if ((mixed && o.scheme == FFTH_CG) || o.scheme == FFTH_CG3) {   // three-term CG (inner) solve
       xf = XF_R3;
       fused = true;
     } else if (P->L.nf32 >= 3) {
@@ -757,9 +758,9 @@ template <typename T> ffth_status run_plain(ffth_plan* P, const Desc* d, int nl)
 // Three-term CG from x_0 = 0 (scheme FFTH_CG3): b = -Gamma0 * P_rhs into the
 // residual slot (r_0 = b; the zero right-hand-side guard and ||b|| from its
 // sums), the start pass, then fused iterations until the recursive residual
-// meets the tolerance.  x_k sits in slot k & 1 (f(0) or f(2)); the result is
-// copied from the last slot to the FP64 output (FP32: into slot 0, which the
-// finish widens).
+// meets the tolerance.  The last x ends in slot f(0) (formed by the finish
+// kernel when the last iteration was even); FP64 copies it to the output,
+// FP32 widens it in the common finish.
 template <typename T> ffth_status run_cg3(ffth_plan* P, int nl) {
   const ffth_opts& o = P->opts;
   ffth_status s;
@@ -778,17 +779,18 @@ template <typename T> ffth_status run_cg3(ffth_plan* P, int nl) {
     it += k;
     if ((s = read_states(P)) != FFTH_OK) return s;
   }
+  // the last x of solves that stopped after an even iteration
+  {
+    ProfScope ps(P, C_POINT, nl);
+    HIPCHK(Launch<T>::cg3_finish(dim3(ms_blocks(P->nvox), nl), P->stream, dptr(P, R_MAIN), 6L * P->nvox));
+  }
   const size_t bytes = (size_t)P->nvox * 6 * sizeof(T);
-  for (int l = 0; l < nl; ++l) {
-    const Desc& m = P->h_desc[desc_slot(P, R_MAIN, l)];
-    const SolverState& st = P->h_state[l];
-    const void* last = (st.iters & 1) ? m.x1 : m.x;
-    if (sizeof(T) == 8) {
+  if (sizeof(T) == 8) {   // FP64: x_k ends in slot 0, copied to the output
+    for (int l = 0; l < nl; ++l) {
+      const Desc& m = P->h_desc[desc_slot(P, R_MAIN, l)];
       double* eps = (double*)P->h_desc[desc_slot(P, R_POST, l)].x;
-      if (st.flag == FLAG_ZERO_RHS) HIPCHK(hipMemsetAsync(eps, 0, bytes, P->stream));
-      else HIPCHK(hipMemcpyAsync(eps, last, bytes, hipMemcpyDeviceToDevice, P->stream));
-    } else if (last != m.x && st.flag != FLAG_ZERO_RHS) {
-      HIPCHK(hipMemcpyAsync(m.x, last, bytes, hipMemcpyDeviceToDevice, P->stream));
+      if (P->h_state[l].flag == FLAG_ZERO_RHS) HIPCHK(hipMemsetAsync(eps, 0, bytes, P->stream));
+      else HIPCHK(hipMemcpyAsync(eps, m.x, bytes, hipMemcpyDeviceToDevice, P->stream));
     }
   }
   return FFTH_OK;
@@ -819,9 +821,10 @@ struct Job {
 
 // Staging for the combined descriptor arrays of one round: a device array and
 // its pinned host copy of `cap` descriptors, filled from `cursor` on.  Each
-// job is in one phase per round, so the active loads of every job of a round
-// fit in one slot each; the host copy is not rewritten before the streams the
-// round's uploads were queued on have drained.
+// job is in one phase per round, so a round stages each load at most twice
+// (the sweep of a load whose inner solve owes its last x also stages that
+// finish); the host copy is not rewritten before the streams the round's
+// uploads were queued on have drained.
 struct Stage {
   Desc* d;
   Desc* h;
@@ -909,8 +912,28 @@ ffth_status group_issue(std::vector<Job*>& jobs, Stage& st, int* kin_out) {
     g_last_error = "inner-solve descriptors do not match the launch's spectrum precision";
     return FFTH_ERR_INVALID;
   }
+  // inner solves that ended after an even iteration owe their last x, which
+  // the sweep of this round adds: formed first (once: the host launches it
+  // in the round after the solve stopped, the only sweep round that follows)
+  const int fromF = st.cursor;
+  int cntF = 0;
+  if (o.scheme == FFTH_CG) {
+    for (Job* J : jobs) {
+      if (J->phase != PH_A) continue;
+      for (int l = 0; l < J->nl && st.cursor < st.cap; ++l)
+        if (J->P->h_state[J->nl + l].xpend) {
+          st.h[st.cursor++] = J->P->h_desc[desc_slot(J->P, R_INNER, l)];
+          ++cntF;
+        }
+    }
+  }
   hipStream_t sm = dims->stream;
   const Desc* d;
+  if ((s = stage_upload(sm, st, fromF, cntF, &d)) != FFTH_OK) return s;
+  if (cntF > 0) {
+    ProfScope ps(dims, C_POINT, cntF);
+    HIPCHK(Launch<float>::cg3_finish(dim3(ms_blocks(dims->nvox), cntF), sm, d, 6L * dims->nvox));
+  }
   if ((s = stage_upload(sm, st, from[0], cnt[0], &d)) != FFTH_OK) return s;
   if ((s = apply<double>(dims, d, cnt[0], XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER)) != FFTH_OK) return s;
   if ((s = stage_upload(sm, st, from[1], cnt[1], &d)) != FFTH_OK) return s;
@@ -1054,7 +1077,7 @@ void build_solve_descs(ffth_plan* P, int nl, const double* E, double* eps, bool 
     if (o.precision == FFTH_MIXED) {
       // later sweeps: x += delta fused; full FP64 residual kept for its projection
       md.delta = f32_ptr(P, l, 0);
-      md.delta1 = o.scheme == FFTH_CG ? f32_ptr(P, l, 2) : nullptr;
+      md.delta_gate = o.scheme == FFTH_CG ? 1 : 0;
       md.r = f64_ptr(P, l, 0);
       md.r_f32 = 0;
       pr.r = f64_ptr(P, l, 0);
@@ -1878,8 +1901,8 @@ ffth_status ffth_server_create(ffth_server** out, void* arena, size_t arena_byte
     g_last_error = "arena must be 256-byte aligned; serving runs the mixed-precision solver";
     return FFTH_ERR_INVALID;
   }
-  // every running request has at most 6 loads, each staged once per step
-  const int cap = 6 * max_running;
+  // every running request has at most 6 loads, each staged at most twice per step
+  const int cap = 12 * max_running;
   const size_t stage_bytes = al((size_t)cap * sizeof(Desc));
   if (arena_bytes <= stage_bytes) {
     g_last_error = "arena too small";

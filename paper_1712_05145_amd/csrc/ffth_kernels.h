@@ -172,6 +172,10 @@ __device__ __forceinline__ double c0_ip(double lam0, double mu0, const double (&
   return lam0 * ta * tb + 2.0 * mu0 * ab;
 }
 
+// Residual slot of iteration k in the three-term CG: r_k sits in slot k mod 2
+// (r_{k+1} overwrites r_{k-1}, which iteration k reads first).
+__device__ __forceinline__ void* rslot(const Desc& d, int k) { return (k & 1) ? d.r1 : d.r; }
+
 // ---------------------------------------------------------------------------
 // x-pass, forward: polarization + real-to-complex FFT along axis 2.
 // ---------------------------------------------------------------------------
@@ -254,13 +258,9 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
   const T beta = (T)d.st->beta;
   const T ts = d.h16 ? (T)(d.tau_scale / d.st->dscale) : T(1);   // binary16 spectrum scale
   const bool first = d.st->first != 0;
-  // correction fused into the FP64 residual pass: with a three-term inner CG it
-  // sits in the slot of the inner iteration count's parity (none after 0 iterations)
-  const float* dl = d.delta;
-  if (d.delta1) {
-    const int it = d.st2->iters;
-    dl = it == 0 ? nullptr : (it & 1) ? d.delta1 : d.delta;
-  }
+  // correction fused into the FP64 residual pass (the three-term inner CG
+  // leaves none after 0 iterations)
+  const float* dl = (d.delta_gate && d.st2->iters == 0) ? nullptr : d.delta;
 
   for (int v = threadIdx.x; v < ROWS * N2; v += NTB) {
     const int rr = v / N2, i2 = v % N2;
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
         // <r, r>_C0, <r, C r> (= <r, A r>_C0 on compatible r) and ||r||^2
         // (binary16 spectrum: tau carries the factor that keeps the transforms
         // in range, with the right-hand side's RMS divided out)
-        const T* rp = (const T*)((d.st->iters & 1) ? d.r1 : d.r);
+        const T* rp = (const T*)rslot(d, d.st->iters);
         T r[6], cr[6];
         double rd[6];
 #pragma unroll
@@ -587,12 +587,17 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
 // Three-term CG iteration fused into one x-pass: inverse FFT of eta_k =
 // -Gamma0 * (C - C0) r_k, the recurrences
 //   w = A r_k = r_k - eta_k
-//   r_{k+1} = omega (r_k - gamma w) + (1 - omega) r_{k-1}
-//   x_{k+1} = omega (x_k + gamma r_k) + (1 - omega) x_{k-1}
+//   r_{k+1} = omega_k (r_k - gamma_k w) + (1 - omega_k) r_{k-1}
+//   x_{k+1} = omega_k (x_k + gamma_k r_k) + (1 - omega_k) x_{k-1}
 // (gamma = <r,r>_C0 / <r,Ar>_C0, omega from the previous scalars; the first
-// step has omega = 1; x_0 = 0 is never stored), the sums of r_{k+1} and the forward FFT of
-// (C - C0) r_{k+1}, written back over the block's own spectrum rows.
-// Iterates ping-pong between two slots: r_k, x_k sit in slot (k & 1).
+// step has omega = 1; x_0 = 0 is never stored), the sums of r_{k+1} and the
+// forward FFT of (C - C0) r_{k+1}, written back over the block's own spectrum
+// rows.  r_k sits in slot k mod 2.  The x recurrence is applied two steps at a
+// time: the odd iteration k forms x_k (from x_{k-1}, x_{k-2}, r_{k-1} and the
+// previous scalars) and x_{k+1} from the same data plus r_k, the two residuals
+// it reads anyway, so x is read and written on every other iteration only
+// (the pair x_{k+1}, x_k overwrites x_{k-1}, x_{k-2} in slots x, x1).  A solve
+// that stops after an even iteration forms its last x in k_cg3_finish.
 // ---------------------------------------------------------------------------
 template <typename T, int N2, bool ISO, int ROWS = xi_rows<T>(N2), int NTB = NT, typename S = C2<T>, int PLAN = 0>
 __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, long rows_total, long nvox) {
@@ -612,12 +617,16 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
 
   const int it = d.st->iters;
   const bool first = d.st->first != 0;
+  const bool xstep = (it & 1) != 0;   // this iteration forms x_k and x_{k+1}
   const T gam = (T)d.st->alpha;
   const T om = first ? T(1) : (T)d.st->beta;
-  const T* xc = (const T*)((it & 1) ? d.x1 : d.x);
-  const T* rc = (const T*)((it & 1) ? d.r1 : d.r);
-  T* xo = (T*)((it & 1) ? d.x : d.x1);
-  T* ro = (T*)((it & 1) ? d.r : d.r1);
+  const T gp = (T)d.st->alpha_prev;   // gamma_{k-1}
+  const T op = (T)d.st->beta_prev;    // omega_{k-1} (1 at k = 1)
+  const T* rc = (const T*)rslot(d, it);        // r_k
+  const T* rpv = (const T*)rslot(d, it + 1);   // r_{k-1}, overwritten by r_{k+1}
+  T* ro = (T*)rslot(d, it + 1);
+  T* xn = (T*)d.x;    // x_{k-1} in, x_{k+1} out (odd k)
+  T* xo = (T*)d.x1;   // x_{k-2} in, x_k out
   const T* mat = mat_of<T>(d);
   const T ts = d.h16 ? (T)(d.tau_scale / d.st->dscale) : T(1);   // binary16 spectrum scale
   double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
@@ -632,16 +641,14 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
       // slots may alias the inputs as far as the compiler knows)
       // (the iterates are streamed: each is read once per iteration, long after
       // it was written, so the accesses carry the non-temporal hint)
-      T rk[6], rp[6], xk[6], xp[6];
+      T rk[6], rp[6], xa[6], xb[6];
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         rk[c] = __builtin_nontemporal_load(rc + c * nvox + vox);
-        if (!first) {
-          rp[c] = __builtin_nontemporal_load(ro + c * nvox + vox);
-          xk[c] = __builtin_nontemporal_load(xc + c * nvox + vox);
-          // x_{k-1} = x_0 = 0 at k = 1: its slot is never written in this solve
-          xp[c] = it == 1 ? T(0) : __builtin_nontemporal_load(xo + c * nvox + vox);
-        }
+        rp[c] = first ? T(0) : __builtin_nontemporal_load(rpv + c * nvox + vox);
+        // x_0 = 0 is never stored: the pair is read from the third iteration on
+        xa[c] = (xstep && it > 1) ? __builtin_nontemporal_load(xn + c * nvox + vox) : T(0);
+        xb[c] = (xstep && it > 1) ? __builtin_nontemporal_load(xo + c * nvox + vox) : T(0);
       }
       T rn[6];
 #pragma unroll
@@ -653,16 +660,14 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
           const T eta = h ? e.y : e.x;
           const T r = rk[c];
           const T w = r - eta;
-          T xn, rv;
-          if (first) {
-            rv = r - gam * w;
-            xn = gam * r;
-          } else {
-            rv = om * (r - gam * w) + (T(1) - om) * rp[c];
-            xn = om * (xk[c] + gam * r) + (T(1) - om) * xp[c];
-          }
+          const T rv = first ? r - gam * w : om * (r - gam * w) + (T(1) - om) * rp[c];
           __builtin_nontemporal_store(rv, ro + c * nvox + vox);
-          __builtin_nontemporal_store(xn, xo + c * nvox + vox);
+          if (xstep) {
+            const T xk = op * (xa[c] + gp * rp[c]) + (T(1) - op) * xb[c];
+            const T x1 = om * (xk + gam * r) + (T(1) - om) * xa[c];
+            __builtin_nontemporal_store(x1, xn + c * nvox + vox);
+            __builtin_nontemporal_store(xk, xo + c * nvox + vox);
+          }
           rn[c] = rv;
         }
       }
@@ -688,6 +693,33 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
   store_rows_r2c<T, N2, ROWS, NTB, S>(spec, z, row0, rows_total);
   double sums[3] = {acc0, acc1, acc2};
   block_sums<3, NTB>(sums, d.part_i + blockIdx.x, gridDim.x);
+}
+
+// Three-term CG: the last x of loads whose solve stopped after an even
+// iteration k (their state says so).  The odd iteration k - 1 left x_k and
+// x_{k-1} in the slots x and x1; x_{k+1} = omega_k (x_k + gamma_k r_k) +
+// (1 - omega_k) x_{k-1} goes to x, x_k to x1 (k = 0: x_1 = gamma_0 r_0).
+// n = 6 x voxels.  Run once per stopped solve (the update is not idempotent).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cg3_finish(const Desc* __restrict__ descs, long n) {
+  const Desc& d = descs[blockIdx.y];
+  const SolverState* st = d.st;
+  if (st->active || !st->xpend) return;
+  const int k = st->iters - 1;
+  const T gam = (T)st->alpha;
+  const T om = k == 0 ? T(1) : (T)st->beta;
+  const T* rk = (const T*)rslot(d, k);
+  T* xn = (T*)d.x;
+  T* xo = (T*)d.x1;
+  for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) {
+    if (k == 0) {
+      xn[i] = gam * rk[i];
+    } else {
+      const T xa = xn[i], xb = xo[i];
+      xn[i] = om * (xa + gam * rk[i]) + (T(1) - om) * xb;
+      xo[i] = xa;
+    }
+  }
 }
 
 // BiCGSTAB: apply the last iteration's x += alpha p + omega s to loads that

@@ -144,6 +144,9 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
       st->rr = sf[0];
       st->alpha = sf[0] / sf[1];
       st->beta = 1.0;
+      st->alpha_prev = 0.0;
+      st->beta_prev = 1.0;
+      st->xpend = 0;
       st->first = 1;
       break;
     }
@@ -156,18 +159,28 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
       const double den = 1.0 - (g / st->alpha) * (si[0] / st->rr) / st->beta;
       const double om = 1.0 / den;
       st->first = 0;
+      // stop before the scalars advance: a solve that stops keeps gamma_k,
+      // omega_k (and gamma_{k-1}, omega_{k-1}) of its last iteration k, from
+      // which k_cg3_finish forms x_{k+1} when k was even
       if (st->res < st->tol) {
         st->flag = FLAG_CONVERGED;
         st->active = 0;
-      } else if (!(si[1] > 0.0) || !(om == om) || !(fabs(om) < 1e6)) {
+      } else if (!(si[1] > 0.0) || !(om == om) || !(fabs(om) < 1e6) || !(st->res == st->res) || st->res > 1e6) {
         st->flag = FLAG_DIVERGED;
+        st->active = 0;
+      } else if (st->total >= st->max_iter) {
+        // iteration budget (over all solves sharing the state: the mixed
+        // scheme's inner solves count together) spent; flag stays RUNNING
         st->active = 0;
       } else {
         st->rr = si[0];
+        st->alpha_prev = st->alpha;
+        st->beta_prev = st->beta;
         st->alpha = g;
         st->beta = om;
-        fin_check(st);
       }
+      // x is formed on odd iterations: after an even last one (iters odd) it is owed
+      if (!st->active) st->xpend = st->iters & 1;
       break;
     }
     case FIN_BI_INIT:
@@ -231,6 +244,7 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
       in->rr = si[1];
       in->first = 1;
       in->iters = 0;
+      in->xpend = 0;
       in->flag = FLAG_RUNNING;
       in->res = 1.0;
       break;
@@ -273,6 +287,7 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
         in->rr = si[1];
         in->first = 1;
         in->iters = 0;
+        in->xpend = 0;
         in->flag = FLAG_RUNNING;
         in->res = 1.0;
       }

@@ -163,6 +163,11 @@ template <typename T> hipError_t Launch<T>::bicg_finish(dim3 grid, hipStream_t s
   return hipGetLastError();
 }
 
+template <typename T> hipError_t Launch<T>::cg3_finish(dim3 grid, hipStream_t s, const Desc* d, long n) {
+  hipLaunchKernelGGL((k_cg3_finish<T>), grid, dim3(NT), 0, s, d, n);
+  return hipGetLastError();
+}
+
 template struct Launch<R>;
 
 }  // namespace ffth

@@ -33,6 +33,8 @@ template <typename T> struct Launch {
                          long nvox);
   // BiCGSTAB: the pending x update of loads that stopped (n = 6 * voxels)
   static hipError_t bicg_finish(dim3 grid, hipStream_t s, const Desc* d, long n);
+  // three-term CG: the last x of loads that stopped after an even iteration
+  static hipError_t cg3_finish(dim3 grid, hipStream_t s, const Desc* d, long n);
   static hipError_t ypass(int n1, int v, bool h16, dim3 grid, hipStream_t s, const Desc* d, int dir, int ncols,
                           int ntiles);
   static hipError_t zpass(int n0, int v, bool h16, dim3 grid, hipStream_t s, const Desc* d, int op, int n1, int h,

@@ -27,8 +27,9 @@ struct SolverState {
   double omega;      // BiCGSTAB: omega of the last iteration
   double dscale;     // inner state: RMS of the inner right-hand side (binary16 spectrum scale)
   int32_t pending;   // BiCGSTAB: x += alpha p + omega s of the last iteration not applied yet
-  int32_t pad;
+  int32_t xpend;     // three-term CG: stopped after an even iteration, x of the last one not formed yet
   double tol0;       // inner state: the tightest reduction asked of one inner solve
+  double alpha_prev, beta_prev;  // three-term CG: gamma and omega of the iteration before the current one
 };
 
 enum : int32_t { FLAG_RUNNING = 0, FLAG_CONVERGED = 1, FLAG_DIVERGED = 2, FLAG_ZERO_RHS = 3 };
@@ -46,7 +47,7 @@ struct Desc {
   float* delta;            // FP32 correction fused into the FP64 residual pass (or null)
   float* delta1;           // its second slot when the inner solve is the three-term CG (or null)
   void* x1;                // three-term CG: second iterate slot (x_{k-1}, overwritten by x_{k+1})
-  void* r1;                // three-term CG: second residual slot
+  void* r1;                // three-term CG: second residual slot (r_k in slot k mod 2)
   void* rh;                // BiCGSTAB: shadow residual r^ = r_0
   void* v;                 // BiCGSTAB: v = A p
   void* s;                 // BiCGSTAB: s = r - alpha v
@@ -71,6 +72,8 @@ struct Desc {
   int32_t r_f32;           // residual stored as FP32
   int32_t h16;             // the inner solve keeps its spectrum in binary16
   int32_t nc_out;          // components of out written by the store / accumulate x-pass (0: nc)
+  int32_t delta_gate;      // delta is the three-term inner solve's x: absent while it has no iteration
+  int32_t pad;
 };
 
 // x-pass (forward) modes

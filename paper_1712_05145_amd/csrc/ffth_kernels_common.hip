@@ -147,6 +147,9 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
       st->alpha_prev = 0.0;
       st->beta_prev = 1.0;
       st->xpend = 0;
+      st->best_res = 1.0;
+      st->best_it = 0;
+      st->stalled = 0;
       st->first = 1;
       break;
     }
@@ -172,12 +175,21 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
         // iteration budget (over all solves sharing the state: the mixed
         // scheme's inner solves count together) spent; flag stays RUNNING
         st->active = 0;
+      } else if (st->iters - st->best_it >= CG3_STALL && !(st->res < st->best_res)) {
+        // no new smallest residual for CG3_STALL iterations: the rounding
+        // floor of this precision; flag stays RUNNING
+        st->stalled = 1;
+        st->active = 0;
       } else {
         st->rr = si[0];
         st->alpha_prev = st->alpha;
         st->beta_prev = st->beta;
         st->alpha = g;
         st->beta = om;
+      }
+      if (st->res < st->best_res) {
+        st->best_res = st->res;
+        st->best_it = st->iters;
       }
       // x is formed on odd iterations: after an even last one (iters odd) it is owed
       if (!st->active) st->xpend = st->iters & 1;

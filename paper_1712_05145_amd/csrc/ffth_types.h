@@ -30,7 +30,15 @@ struct SolverState {
   int32_t xpend;     // three-term CG: stopped after an even iteration, x of the last one not formed yet
   double tol0;       // inner state: the tightest reduction asked of one inner solve
   double alpha_prev, beta_prev;  // three-term CG: gamma and omega of the iteration before the current one
+  double best_res;   // three-term CG: smallest residual of the current solve
+  int32_t best_it;   // three-term CG: iteration that reached it
+  int32_t stalled;   // three-term CG: the solve stopped without a new smallest residual for CG3_STALL iterations
 };
+
+// Three-term CG stops a solve whose recursive residual set no new minimum in
+// this many iterations (its rounding floor: an FP32 inner solve asked for more
+// than its arithmetic reaches hands over to the FP64 sweep instead).
+constexpr int CG3_STALL = 64;
 
 enum : int32_t { FLAG_RUNNING = 0, FLAG_CONVERGED = 1, FLAG_DIVERGED = 2, FLAG_ZERO_RHS = 3 };
 

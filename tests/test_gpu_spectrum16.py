@@ -137,3 +137,22 @@ def test_tiny_and_zero_loads(h16):
     assert torch.count_nonzero(eps[0]).item() == 0
     assert res[1]["status"] == 0 and res[2]["status"] == 0
     assert rel_l2(eps[1].cpu().numpy() * 1e20, eps[2].cpu().numpy()) < 1e-9
+
+
+def test_inner_solves_below_their_floor_hand_over():
+    """An inner bound far below what the binary16-spectrum FP32 inner solve can
+    reach: each inner solve stops at its floor (no new smallest residual for 64
+    iterations) and the FP64 sweeps still take the solve to the tolerance,
+    instead of iterating to the budget."""
+    torch = require_gpu()
+    phase, lame = M.centred_sphere(16, young=(1.0, 10.0))
+    lam0, mu0 = M.midpoint_reference(lame)
+    prob = H.make_problem(phase, lam0, mu0, lame=lame)
+    eps_ref, mean_ref, _ = H.solve_order0(prob, [1, 0, 0, 0, 0, 0], "cg", tol=1e-12)
+    s = ffth.Solver(phase, lam0, mu0, lame=lame, precision="mixed", tol=1e-10, inner_tol=1e-9,
+                    spectrum16="force", max_iter=20000)
+    eps, res = s.solve_order0([1, 0, 0, 0, 0, 0])
+    print("inner iterations", res[0]["iters"], "sweeps", res[0]["fp64_applications"], flush=True)
+    assert res[0]["status"] == 0 and res[0]["residual"] < 1e-10
+    assert res[0]["iters"] < 2000
+    assert rel_l2(eps[0].cpu().numpy(), voigt6(eps_ref)) < 1e-6

@@ -569,7 +569,8 @@ def main():
         t = time.perf_counter()
         a = make(precision, 0, 6, scheme, spectrum16)
         b = make(precision, 1, 1, scheme, spectrum16)
-        log(f"{tag}: plans (incl. tile autotuning) in {time.perf_counter() - t:.2f}s; tiles {a.tile_variants}")
+        log(f"{tag}: plans (incl. tile autotuning) in {time.perf_counter() - t:.2f}s; tiles {a.tile_variants}, "
+            f"loads per launch {a.launch_loads}")
         e0 = a.field(6, 6)
         e1 = b.field(6, 1)
         for w in range(warmup):
@@ -589,7 +590,7 @@ def main():
         bad = [r for rs in results for r in rs if r["status"] != 0]
         if bad:
             raise SystemExit(f"{tag}: solve failed: {bad[0]}")
-        tiles = a.tile_variants
+        tiles = a.tile_variants + a.launch_loads   # 8 tile variants, loads per launch FP32 / FP64
         # order-1 right-hand side alone (displacements of the six correctors,
         # pointwise terms, theta), outside the timed steps
         torch.cuda.synchronize()
@@ -681,7 +682,8 @@ def main():
         "inner_iteration": inner_iteration,
         "kernels": kernels,
         "tile_variants": dict(zip(["xfwd_f32", "xfwd_f64", "ypass_f32", "ypass_f64", "zpass_f32", "zpass_f64",
-                                   "xinv_f32", "xinv_f64"], tiles)),
+                                   "xinv_f32", "xinv_f64", "loads_per_launch_f32", "loads_per_launch_f64"],
+                                  tiles)),
     }
     torch.cuda.empty_cache()
 

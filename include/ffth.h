@@ -259,19 +259,36 @@ const char *ffth_profile_name(int32_t category);
 /* Tile variant chosen per pass: out[2*pass + prec], pass 0..3 = x-forward, y,
  * z, x-inverse; prec 0 = FP32, 1 = FP64 (variant 0 = the default shape). */
 ffth_status ffth_tile_variants(ffth_plan *plan, int32_t out[8]);
-/* Pin the tile variants (same layout; each in [0, 4)); results of every
- * variant agree to rounding.  INVALID for a value out of range. */
+/* Pin the tile variants (same layout; each in [0, 6): 0..3 tile shapes with
+ * the default radix order, 4 and 5 the default tile with the radix orders
+ * 4-2-3-5-8-16 and 8-4-2-3-5-16); results of every variant agree to
+ * rounding.  INVALID for a value out of range. */
 ffth_status ffth_set_tile_variants(ffth_plan *plan, const int32_t in[8]);
+/* Loads per launch of the iteration passes, out[prec] (0 = FP32, 1 = FP64):
+ * 0 = every load of the iteration in one launch per pass; k > 0 = the loads
+ * are taken k at a time, each group through all of the iteration's passes
+ * (y, z, y and the x-passes) before the next (load-major order), and the
+ * scalars of all of them finalized together.  Chosen by the autotuner like
+ * the tile variants (0 unless a smaller width is measured faster). */
+ffth_status ffth_launch_loads(ffth_plan *plan, int32_t out[2]);
+/* Pin them (each >= 0); results do not depend on the width (every load's
+ * blocks and sums are the same in any launch).  INVALID for a negative value. */
+ffth_status ffth_set_launch_loads(ffth_plan *plan, const int32_t in[2]);
 
 /* ---- Serving: continuous batching of order-0 solves ----------------------
  * A server owns no device memory: the caller hands it one device arena (the
  * HBM budget).  Requests (one RVE, 1..6 macro strains each, e.g. the six unit
- * loads of an effective-stiffness request) are admitted in arrival order as
- * soon as their memory (ffth_request_bytes) fits the free arena and one of
- * max_running slots is free.  Each ffth_server_step advances every running
- * request by one phase of the mixed-precision solve (an FP64 residual sweep,
- * the compatible projection, or check_every FP32 iterations); requests of the
- * same grid size share every kernel launch.  A completed request returns its
+ * loads of an effective-stiffness request) are admitted while one of
+ * max_running slots is free: the waiting request of least work (voxels x
+ * loads) whose memory (ffth_request_bytes) fits the free arena goes first
+ * (ties: earlier arrival); a request passed over max_running times goes next
+ * as soon as its memory fits, and nothing passes it meanwhile.  Each
+ * ffth_server_step advances every running request by one phase of the
+ * mixed-precision solve (an FP64 residual sweep, the compatible projection,
+ * or check_every FP32 iterations); requests of the same grid size, material
+ * kind and spectrum precision share every kernel launch, and each grid size
+ * is bound to one of four streams (the caller's and three the server
+ * creates), so that sizes run concurrently; a step waits for all of them.  A completed request returns its
  * memory to the arena and its results (mean stresses, i.e. C_eff columns
  * for unit loads) to ffth_poll.  Results do not depend on what else runs:
  * every load keeps its own iteration state and reductions are fixed-order.

@@ -230,6 +230,7 @@ struct ffth_plan {
   int nx64, nx32;         // forward x-pass blocks per precision
   int ni64, ni32;         // inverse x-pass blocks per precision
   int var[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};   // tile variant per pass (xf, y, z, xi) and FP32/FP64
+  int bw[2] = {0, 0};     // loads per launch of the iteration passes, FP32/FP64 (0: all at once)
   std::vector<Desc> h_desc;
   // kernel timing (diagnostics): events bracket every launch when enabled
   bool prof = false;
@@ -394,6 +395,12 @@ template <typename T> int pv(ffth_plan* P, Pass ps) { return P->var[ps][sizeof(T
 
 template <typename T> int xblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->nx64 : P->nx32; }
 template <typename T> int iblocks(ffth_plan* P) { return sizeof(T) == 8 ? P->ni64 : P->ni32; }
+// Loads per launch of the iteration passes for an iteration over nb loads:
+// all of them, unless the plan's width for this precision is smaller.
+template <typename T> int chunk_of(ffth_plan* P, int nb) {
+  const int w = P->bw[sizeof(T) == 8 ? 1 : 0];
+  return w > 0 && w < nb ? w : nb;
+}
 
 template <typename T> ffth_status xfwd(ffth_plan* P, const Desc* d, int nb, int mode, bool h16 = false) {
   ProfScope ps(P, mode == XF_R3 ? (sizeof(T) == 8 ? C_CG3S_64 : C_CG3S) : sizeof(T) == 8 ? C_XF64 : C_XF32, nb);
@@ -460,14 +467,17 @@ template <typename T> ffth_status cg3_start(ffth_plan* P, const Desc* d, int nb,
   return fin(P, d, nb, FIN_CG3_INIT, xblocks<T>(P), 0);
 }
 
-// One three-term CG iteration: y, z (Green operator), y, fused x-pass, scalars.
+// One three-term CG iteration: y, z (Green operator), y, fused x-pass (per
+// group of chunk_of loads), then the scalars of every load.
 template <typename T> ffth_status cg3_iter(ffth_plan* P, const Desc* d, int nb, bool h16) {
   ffth_status s;
   if (nb <= 0) return FFTH_OK;
-  if ((s = yzy<T>(P, d, nb, OP_GAMMA, h16)) != FFTH_OK) return s;
-  {
-    ProfScope ps(P, sizeof(T) == 8 ? C_XCG3_64 : C_XCG3, nb);
-    HIPCHK(Launch<T>::xcg3(P->n[2], P->iso, pv<T>(P, PS_XI), h16, dim3(iblocks<T>(P), nb), P->stream, d, P->rows,
+  const int c = chunk_of<T>(P, nb);
+  for (int i = 0; i < nb; i += c) {
+    const int k = std::min(c, nb - i);
+    if ((s = yzy<T>(P, d + i, k, OP_GAMMA, h16)) != FFTH_OK) return s;
+    ProfScope ps(P, sizeof(T) == 8 ? C_XCG3_64 : C_XCG3, k);
+    HIPCHK(Launch<T>::xcg3(P->n[2], P->iso, pv<T>(P, PS_XI), h16, dim3(iblocks<T>(P), k), P->stream, d + i, P->rows,
                            P->nvox));
   }
   return fin(P, d, nb, FIN_CG3, 0, iblocks<T>(P));
@@ -481,7 +491,7 @@ template <typename T> ffth_status cg3_iter(ffth_plan* P, const Desc* d, int nb, 
 // Choices are cached per (grid, material kind, precision, scheme) for the
 // process.  Grids below 64^3 keep the defaults (launch-bound).
 std::mutex g_tune_mu;
-std::map<std::array<int, 7>, std::array<int, 8>> g_tune_cache;
+std::map<std::array<int, 7>, std::array<int, 10>> g_tune_cache;   // tiles [8], loads per launch [2]
 
 template <class F> double time_launches(hipStream_t st, hipEvent_t e0, hipEvent_t e1, F&& launch) {
   launch();  // warm-up
@@ -556,6 +566,44 @@ void tune_prec(ffth_plan* P, const Desc* d, int nt, int xf_mode, int xi_mode, bo
     P->var[pass][pi] = bv;
   }
   set_blocks(P);
+  // loads per launch, with the chosen tiles: one whole iteration (x-forward
+  // unless fused, y, z, y, x-inverse or the fused pass) over the nt loads,
+  // all in one launch per pass, then w = 1, 2, 4, ... at a time, each group
+  // through every pass before the next
+  P->bw[pi] = 0;
+  if (nt > 1) {
+    const int cw = Launch<T>::y_cols(P->n[1], P->var[PS_Y][pi]), ntl = (ncols + cw - 1) / cw;
+    const int tk = Launch<T>::z_cols(P->n[0], P->var[PS_Z][pi]);
+    const int nzb = (int)((M + tk - 1) / tk) * (P->h / kc);
+    auto iteration = [&](int w) {
+      for (int i = 0; i < nt; i += w) {
+        const int k = std::min(w, nt - i);
+        if (!fused)
+          (void)Launch<T>::xfwd(P->n[2], P->iso, P->var[PS_XF][pi], h16, dim3(xblocks<T>(P), k), P->stream, d + i,
+                                xf_mode, P->rows, P->nvox);
+        (void)Launch<T>::ypass(P->n[1], P->var[PS_Y][pi], h16, dim3(nplanes * ntl, k), P->stream, d + i, -1, ncols,
+                               ntl);
+        (void)Launch<T>::zpass(P->n[0], P->var[PS_Z][pi], h16, dim3(nzb, k), P->stream, d + i, OP_GAMMA, P->n[1],
+                               P->h, 1.0 / (double)P->nvox);
+        (void)Launch<T>::ypass(P->n[1], P->var[PS_Y][pi], false, dim3(nplanes * ntl, k), P->stream, d + i, +1, ncols,
+                               ntl);
+        if (fused)
+          (void)Launch<T>::xcg3(P->n[2], P->iso, P->var[PS_XI][pi], h16, dim3(iblocks<T>(P), k), P->stream, d + i,
+                                P->rows, P->nvox);
+        else
+          (void)Launch<T>::xinv(P->n[2], P->iso, P->var[PS_XI][pi], dim3(iblocks<T>(P), k), P->stream, d + i,
+                                xi_mode, P->rows, P->nvox);
+      }
+    };
+    double best = time_launches(P->stream, e0, e1, [&] { iteration(nt); });
+    for (int w = 1; w < nt; w *= 2) {
+      const double t = time_launches(P->stream, e0, e1, [&] { iteration(w); });
+      if (t < best * 0.98) {   // a width must beat the one-launch iteration by 2%
+        best = t;
+        P->bw[pi] = w;
+      }
+    }
+  }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
 }
@@ -580,6 +628,8 @@ ffth_status autotune(ffth_plan* P) {
     auto it = g_tune_cache.find(key);
     if (it != g_tune_cache.end()) {
       for (int i = 0; i < 8; ++i) P->var[i / 2][i % 2] = it->second[i];
+      P->bw[0] = it->second[8];
+      P->bw[1] = it->second[9];
       set_blocks(P);
       return FFTH_OK;
     }
@@ -655,22 +705,29 @@ ffth_status autotune(ffth_plan* P) {
   }
   HIPCHK(hipStreamSynchronize(P->stream));
   HIPCHK(hipGetLastError());
-  std::array<int, 8> val;
+  std::array<int, 10> val;
   for (int i = 0; i < 8; ++i) val[i] = P->var[i / 2][i % 2];
+  val[8] = P->bw[0];
+  val[9] = P->bw[1];
   std::lock_guard<std::mutex> lk(g_tune_mu);
   g_tune_cache[key] = val;
   return FFTH_OK;
 }
 
-// One full operator application: x-fwd(mode) [fin alpha] y z y x-inv(mode) fin(op)
+// One full operator application: x-fwd(mode) [fin alpha] y z y x-inv(mode)
+// per group of chunk_of loads, then fin(op) for all of them
 template <typename T>
 ffth_status apply(ffth_plan* P, const Desc* d, int nb, int xf, int spec_op, int xi, int fin_op) {
   ffth_status s;
   if (nb <= 0) return FFTH_OK;
-  if ((s = xfwd<T>(P, d, nb, xf)) != FFTH_OK) return s;
-  if (xf == XF_CG && (s = fin(P, d, nb, FIN_CG_ALPHA, xblocks<T>(P), 0)) != FFTH_OK) return s;
-  if ((s = yzy<T>(P, d, nb, spec_op)) != FFTH_OK) return s;
-  if ((s = xinv<T>(P, d, nb, xi)) != FFTH_OK) return s;
+  const int c = chunk_of<T>(P, nb);
+  for (int i = 0; i < nb; i += c) {
+    const int k = std::min(c, nb - i);
+    if ((s = xfwd<T>(P, d + i, k, xf)) != FFTH_OK) return s;
+    if (xf == XF_CG && (s = fin(P, d + i, k, FIN_CG_ALPHA, xblocks<T>(P), 0)) != FFTH_OK) return s;
+    if ((s = yzy<T>(P, d + i, k, spec_op)) != FFTH_OK) return s;
+    if ((s = xinv<T>(P, d + i, k, xi)) != FFTH_OK) return s;
+  }
   if (fin_op >= 0 && (s = fin(P, d, nb, fin_op, xblocks<T>(P), iblocks<T>(P))) != FFTH_OK) return s;
   return FFTH_OK;
 }
@@ -708,13 +765,18 @@ DescSet active_set(ffth_plan* P, Role r, int state_base, int nl, int region) {
 template <typename T> ffth_status bicg_iter(ffth_plan* P, const Desc* d, int nb) {
   ffth_status s;
   if (nb <= 0) return FFTH_OK;
-  if ((s = xfwd<T>(P, d, nb, XF_BI1)) != FFTH_OK) return s;
-  if ((s = yzy<T>(P, d, nb, OP_GAMMA)) != FFTH_OK) return s;
-  if ((s = xinv<T>(P, d, nb, XI_BI1)) != FFTH_OK) return s;
-  if ((s = fin(P, d, nb, FIN_BI_ALPHA, 0, iblocks<T>(P))) != FFTH_OK) return s;
-  if ((s = xfwd<T>(P, d, nb, XF_BI2)) != FFTH_OK) return s;
-  if ((s = yzy<T>(P, d, nb, OP_GAMMA)) != FFTH_OK) return s;
-  if ((s = xinv<T>(P, d, nb, XI_BI2)) != FFTH_OK) return s;
+  const int c = chunk_of<T>(P, nb);
+  for (int i = 0; i < nb; i += c) {   // per group of loads (load-major)
+    const int k = std::min(c, nb - i);
+    const Desc* g = d + i;
+    if ((s = xfwd<T>(P, g, k, XF_BI1)) != FFTH_OK) return s;
+    if ((s = yzy<T>(P, g, k, OP_GAMMA)) != FFTH_OK) return s;
+    if ((s = xinv<T>(P, g, k, XI_BI1)) != FFTH_OK) return s;
+    if ((s = fin(P, g, k, FIN_BI_ALPHA, 0, iblocks<T>(P))) != FFTH_OK) return s;
+    if ((s = xfwd<T>(P, g, k, XF_BI2)) != FFTH_OK) return s;
+    if ((s = yzy<T>(P, g, k, OP_GAMMA)) != FFTH_OK) return s;
+    if ((s = xinv<T>(P, g, k, XI_BI2)) != FFTH_OK) return s;
+  }
   return fin(P, d, nb, FIN_BI_OMEGA, 0, iblocks<T>(P));
 }
 
@@ -1739,6 +1801,25 @@ ffth_status ffth_set_tile_variants(ffth_plan* P, const int32_t in[8]) {
   }
   for (int i = 0; i < 8; ++i) P->var[i / 2][i % 2] = in[i];
   set_blocks(P);
+  return FFTH_OK;
+}
+
+ffth_status ffth_launch_loads(ffth_plan* P, int32_t out[2]) {
+  if (!P || !out) return FFTH_ERR_INVALID;
+  out[0] = P->bw[0];
+  out[1] = P->bw[1];
+  return FFTH_OK;
+}
+
+ffth_status ffth_set_launch_loads(ffth_plan* P, const int32_t in[2]) {
+  g_last_error.clear();
+  if (!P || !in) return FFTH_ERR_INVALID;
+  if (in[0] < 0 || in[1] < 0) {
+    g_last_error = "loads per launch must be >= 0";
+    return FFTH_ERR_INVALID;
+  }
+  P->bw[0] = in[0];
+  P->bw[1] = in[1];
   return FFTH_OK;
 }
 

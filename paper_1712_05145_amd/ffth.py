@@ -97,6 +97,8 @@ SIGNATURES = [
     ("ffth_profile_name", ctypes.c_char_p, [ctypes.c_int32]),
     ("ffth_tile_variants", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     ("ffth_set_tile_variants", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    ("ffth_launch_loads", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    ("ffth_set_launch_loads", ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
     ("ffth_request_bytes", ctypes.c_size_t,
      [ctypes.POINTER(ctypes.c_int32), ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ffth_opts)]),
     ("ffth_server_create", ctypes.c_int,
@@ -197,6 +199,17 @@ def ffth_tile_variants(plan):
 def ffth_set_tile_variants(plan, variants):
     arr = (ctypes.c_int32 * 8)(*[int(v) for v in variants])
     _check(load().ffth_set_tile_variants(plan, arr), "ffth_set_tile_variants")
+
+
+def ffth_launch_loads(plan):
+    out = (ctypes.c_int32 * 2)()
+    _check(load().ffth_launch_loads(plan, out), "ffth_launch_loads")
+    return list(out)
+
+
+def ffth_set_launch_loads(plan, widths):
+    arr = (ctypes.c_int32 * 2)(*[int(v) for v in widths])
+    _check(load().ffth_set_launch_loads(plan, arr), "ffth_set_launch_loads")
 
 
 def ffth_size_supported(n):
@@ -377,6 +390,15 @@ class Solver:
     @tile_variants.setter
     def tile_variants(self, v):
         ffth_set_tile_variants(self.plan, v)
+
+    @property
+    def launch_loads(self):
+        """Loads per launch of the iteration passes [FP32, FP64] (0: all at once)."""
+        return ffth_launch_loads(self.plan)
+
+    @launch_loads.setter
+    def launch_loads(self, v):
+        ffth_set_launch_loads(self.plan, v)
 
     def _out(self, out, nl):
         if out is None:

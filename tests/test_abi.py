@@ -183,3 +183,11 @@ def test_noalloc_green_rejects_before_touching_the_device():
                                         None) == ffth.FFTH_ERR_INVALID
     assert lib.ffth_green_apply_noalloc(ok, 1.0, 1.0, ctypes.c_void_p(16), ctypes.c_void_p(16), 7,
                                         None) == ffth.FFTH_ERR_INVALID
+
+
+def test_launch_loads_need_a_plan():
+    """The loads-per-launch getter and setter refuse a null plan (no GPU)."""
+    lib = ffth.load()
+    arr = (ctypes.c_int32 * 2)(1, 1)
+    assert lib.ffth_launch_loads(None, arr) == ffth.FFTH_ERR_INVALID
+    assert lib.ffth_set_launch_loads(None, arr) == ffth.FFTH_ERR_INVALID

@@ -342,6 +342,44 @@ def test_every_tile_variant_solve_parity(sphere16_oracle, variant, scheme):
     assert ok
 
 
+@pytest.mark.parametrize("scheme,precision", [("cg", "mixed"), ("basic", "mixed"), ("cg", "fp64"),
+                                              ("bicgstab", "fp64"), ("cg3", "fp64"), ("cg3", "fp32")])
+def test_loads_per_launch_bit_identical(sphere16_oracle, scheme, precision):
+    """Loads taken one and four at a time through every pass of an iteration
+    (load-major order) give the results of one launch per pass bit for bit:
+    each load's blocks and sums are the same in any launch.  The one-launch
+    results match the oracle (the FP32-only solve at its own tolerance)."""
+    torch = require_gpu()
+    print("case launch loads", scheme, precision, flush=True)
+    phase, lame, lam0, mu0, ceff, corr, _ = sphere16_oracle
+    tol = 1e-5 if precision == "fp32" else 1e-10
+    out = {}
+    for w in (0, 1, 4):
+        s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, scheme=scheme, precision=precision, tol=tol,
+                        max_iter=5000, autotune=False)
+        s.launch_loads = [w, w]
+        assert s.launch_loads == [w, w]
+        eps, res = s.solve_order0(np.eye(6))
+        assert all(r["status"] == 0 for r in res), [r["status"] for r in res]
+        out[w] = (eps.cpu().numpy(), np.array([r["mean_stress"] for r in res]), [r["iters"] for r in res])
+        s.close()
+    for w in (1, 4):
+        assert np.array_equal(out[w][0], out[0][0]), w
+        assert np.array_equal(out[w][1], out[0][1]), w
+        assert out[w][2] == out[0][2], w
+    bar = 1e-3 if precision == "fp32" else 1e-6
+    for J in range(6):
+        assert rel_l2(out[0][0][J], voigt6(corr[J])) < bar, J
+
+
+def test_loads_per_launch_negative_rejected():
+    torch = require_gpu()
+    s = _uniform_solver(torch, (8, 8, 8))
+    with pytest.raises(ffth.FFTHError):
+        s.launch_loads = [-1, 0]
+    assert s.launch_loads == [0, 0]
+
+
 def test_autotuned_plan_matches_default_tiles():
     """The tuner's choice at 64^3 is a valid variant set and the solve agrees
     with the default tiles (same operator, reductions in another order)."""
@@ -352,11 +390,12 @@ def test_autotuned_plan_matches_default_tiles():
     out = {}
     for tune in (True, False):
         s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, precision="mixed", tol=1e-9, autotune=tune)
-        v = s.tile_variants
-        print("variants", tune, v, flush=True)
+        v, w = s.tile_variants, s.launch_loads
+        print("variants", tune, v, "loads per launch", w, flush=True)
         assert len(v) == 8 and all(0 <= x < ffth.TILE_VARIANTS for x in v)
+        assert len(w) == 2 and all(0 <= x < 6 for x in w)
         if not tune:
-            assert v == [0] * 8
+            assert v == [0] * 8 and w == [0, 0]
         _, res = s.solve_order0(np.eye(6))
         assert all(r["status"] == 0 for r in res)
         out[tune] = np.array([r["mean_stress"] for r in res]).T

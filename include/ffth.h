@@ -309,6 +309,17 @@ ffth_status ffth_server_step(ffth_server *srv, int32_t *running, int32_t *waitin
  * and the id is released.  FFTH_ERR_CANCELLED for cancelled requests. */
 ffth_status ffth_poll(ffth_server *srv, uint64_t request_id, ffth_result *res);
 ffth_status ffth_cancel(ffth_server *srv, uint64_t request_id);
+/* Multi-size launches: with the three-term CG inner solve, the inner
+ * iterations of the running requests whose grids have all three axis lengths
+ * in {16, 24, 32, 48, 64, 96, 128} run as one launch per pass across the grid
+ * sizes that share a stream (more grids than streams; per material kind and
+ * spectrum precision), each load with the default tile shape of its lengths
+ * (a grid alone on its stream keeps the per-size kernels, with the same
+ * tiles); such requests' plans are not autotuned, so their results equal the
+ * plan path's with autotuning off, bit for bit.
+ * multi_iterations: inner iterations run that way so far; multi_max_grids: the most
+ * distinct grids one of those launches carried. */
+ffth_status ffth_server_stats(ffth_server *srv, int64_t *multi_iterations, int32_t *multi_max_grids);
 ffth_status ffth_server_destroy(ffth_server *srv);
 
 /* ---- Allocation-free Green operator application ----------------------

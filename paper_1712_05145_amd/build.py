@@ -28,6 +28,7 @@ UNITS = [
     ("ffth_kernels_fft.hip", "k_fft_f32.o", ["-DFFTH_REAL=float"]),
     ("ffth_kernels_fft.hip", "k_fft_f64.o", ["-DFFTH_REAL=double"]),
     ("ffth_kernels_common.hip", "k_common.o", []),
+    ("ffth_kernels_multi.hip", "k_multi.o", []),
     ("ffth_host.hip", "host.o", []),
     ("ffth_noalloc.hip", "noalloc.o", []),
 ]

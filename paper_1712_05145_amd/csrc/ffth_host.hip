@@ -347,6 +347,7 @@ Desc base_desc(ffth_plan* P, int l) {
   d.inv_nvox = 1.0 / (double)P->nvox;
   d.tau_scale = 1.0;
   d.op_scale = 1.0 / (double)P->nvox;
+  for (int a = 0; a < 3; ++a) d.n[a] = P->n[a];
   return d;
 }
 
@@ -926,12 +927,23 @@ ffth_status enter_inner(Job& J) {
   return FFTH_OK;
 }
 
+// Inner iterations that a round leaves to a multi-size launch (three-term CG
+// inner solves of a grid in the multi-size set): the staged range of the
+// group's inner descriptors and the iterations the group asks for.
+struct InnerSet {
+  bool deferred = false;
+  int from = 0, cnt = 0, kin = 0;
+};
+
 // Queue one round for a group of mixed-precision jobs sharing grid size,
 // material kind, scheme and spectrum precision, on the first job's stream:
 // the launches of every phase and the state read-back of every job.  Nothing
 // waits for the device; group_advance runs once the stream has drained.
-// *kin receives the inner iterations queued.
-ffth_status group_issue(std::vector<Job*>& jobs, Stage& st, int* kin_out) {
+// *kin receives the inner iterations queued.  With defer set (and a grid of
+// the multi-size set), the inner iterations and the read-backs of the jobs in
+// the inner phase are left to the caller (*defer says which loads), who
+// queues them on the same stream.
+ffth_status group_issue(std::vector<Job*>& jobs, Stage& st, int* kin_out, InnerSet* defer = nullptr) {
   *kin_out = 0;
   if (jobs.empty()) return FFTH_OK;
   ffth_plan* dims = jobs[0]->P;
@@ -991,6 +1003,13 @@ ffth_status group_issue(std::vector<Job*>& jobs, Stage& st, int* kin_out) {
   }
   hipStream_t sm = dims->stream;
   const Desc* d;
+  // inner loads first: their descriptors and the start pass of fresh solves
+  const Desc* din;
+  if ((s = stage_upload(sm, st, from[3], cnt[3], &din)) != FFTH_OK) return s;
+  const int nIN = cnt[3];
+  if (o.scheme == FFTH_CG && (s = cg3_start<float>(dims, din, nFresh, dims->h16)) != FFTH_OK) return s;
+  const bool deferred = defer && o.scheme == FFTH_CG && multi_grid(dims->n);
+  if (deferred) *defer = InnerSet{true, from[3], nIN, kin};
   if ((s = stage_upload(sm, st, fromF, cntF, &d)) != FFTH_OK) return s;
   if (cntF > 0) {
     ProfScope ps(dims, C_POINT, cntF);
@@ -1002,12 +1021,18 @@ ffth_status group_issue(std::vector<Job*>& jobs, Stage& st, int* kin_out) {
   if ((s = apply<double>(dims, d, cnt[1], XF_LS, OP_GAMMA, XI_RESID, FIN_OUTER_P)) != FFTH_OK) return s;
   if ((s = stage_upload(sm, st, from[2], cnt[2], &d)) != FFTH_OK) return s;
   if ((s = apply<float>(dims, d, cnt[2], XF_C0, OP_GAMMA, XI_PROJ, FIN_PROJ)) != FFTH_OK) return s;
-  if ((s = stage_upload(sm, st, from[3], cnt[3], &d)) != FFTH_OK) return s;
-  const int nIN = cnt[3];
-  if (o.scheme == FFTH_CG && (s = cg3_start<float>(dims, d, nFresh, dims->h16)) != FFTH_OK) return s;
+  if (deferred) {
+    for (Job* J : jobs) J->fresh = false;
+    for (Job* J : jobs)
+      if (J->phase != PH_INNER)
+        HIPCHK(hipMemcpyAsync(J->P->h_state, J->P->d_state, J->P->L.nstate * sizeof(SolverState),
+                              hipMemcpyDeviceToHost, sm));
+    *kin_out = kin;
+    return FFTH_OK;
+  }
   for (int j = 0; j < kin && nIN > 0; ++j) {
-    if (o.scheme == FFTH_BASIC) s = apply<float>(dims, d, nIN, XF_MATVEC, OP_GAMMA, XI_BS_INNER, FIN_BS);
-    else s = cg3_iter<float>(dims, d, nIN, dims->h16);
+    if (o.scheme == FFTH_BASIC) s = apply<float>(dims, din, nIN, XF_MATVEC, OP_GAMMA, XI_BS_INNER, FIN_BS);
+    else s = cg3_iter<float>(dims, din, nIN, dims->h16);
     if (s != FFTH_OK) return s;
   }
   for (Job* J : jobs) J->fresh = false;
@@ -1879,6 +1904,8 @@ struct ffth_server {
   ffth_opts opts{};
   int max_running = 0;
   int max_bypass = 0;                      // admissions that may pass a waiting request
+  int64_t multi_iterations = 0;            // inner iterations run as multi-size launches
+  int32_t multi_max_grids = 0;             // most distinct grids in one multi-size launch
   Stage stage{nullptr, nullptr, 0, 0};
   FreeList free_;                          // free ranges of the arena
   std::deque<Request*> waiting;
@@ -1936,7 +1963,12 @@ ffth_status admit(ffth_server* S) {
     r->placed = true;
     r->prob.lame = r->iso ? r->table.data() : nullptr;
     r->prob.stiffness = r->iso ? nullptr : r->table.data();
-    ffth_status st = ffth_plan_create(&r->P, &r->prob, &S->opts, r->nl, 0, S->arena + off, r->ws_bytes,
+    // grids whose inner iterations run as multi-size launches keep the
+    // default tiles (those launches use them), so that every pass of the
+    // request is what the plan path computes with autotuning off
+    ffth_opts po = S->opts;
+    if (po.scheme == FFTH_CG && multi_grid(r->n)) po.autotune = 0;
+    ffth_status st = ffth_plan_create(&r->P, &r->prob, &po, r->nl, 0, S->arena + off, r->ws_bytes,
                                       stream_for(S, r->n));
     if (st != FFTH_OK) {
       r->P = nullptr;
@@ -1955,6 +1987,110 @@ ffth_status admit(ffth_server* S) {
     r->job.nl = r->nl;
     r->state = 1;
     S->running.push_back(r);
+  }
+  return FFTH_OK;
+}
+
+
+using GroupMap = std::map<std::tuple<int, int, int, bool, bool>, std::vector<Job*>>;
+
+// The inner iterations the groups of a step deferred (grids of the
+// multi-size set), as one launch per pass for every group of one size
+// stream, material kind and spectrum precision, on that stream after the
+// groups' rounds (grids share a stream when there are more of them than
+// streams; their launches would run one after the other anyway, so merging
+// them costs no concurrency and saves launches): the staged inner
+// descriptors of those groups are copied into one array, each with the
+// block count of its fused pass for the finalize.  Every group of a set runs
+// the smallest of the iteration counts its groups asked for (kin updated);
+// the states of their jobs in the inner phase are read back after the last
+// iteration.
+ffth_status issue_merged(ffth_server* S, GroupMap& groups, const std::vector<InnerSet>& inner,
+                         std::vector<int>& kin) {
+  size_t g = 0;
+  for (hipStream_t m : S->streams) {
+    for (int iso = 0; iso < 2; ++iso) {
+      for (int h16 = 0; h16 < 2; ++h16) {
+        const int from = S->stage.cursor;
+        int cnt = 0, kmin = INT32_MAX;
+        struct Seg {
+          int first, count, nb[3];
+        };
+        std::vector<Seg> segs;   // one per grid with inner loads, descriptors consecutive from `from`
+        std::vector<size_t> members;
+        g = 0;
+        for (auto& kv : groups) {
+          const InnerSet& is = inner[g];
+          const ffth_plan* P0 = kv.second[0]->P;
+          if (is.deferred && P0->stream == m && P0->iso == (iso != 0) && P0->h16 == (h16 != 0)) {
+            members.push_back(g);
+            kmin = std::min(kmin, is.kin);
+            if (S->stage.cursor + is.cnt > S->stage.cap) {
+              g_last_error = "descriptor staging area too small for the step";
+              return FFTH_ERR_INVALID;
+            }
+            Seg sg{cnt, is.cnt, {0, 0, 0}};
+            multi_blocks(P0->n, sg.nb);
+            for (int i = 0; i < is.cnt; ++i) {
+              Desc dd = S->stage.h[is.from + i];
+              dd.nblk_multi = sg.nb[2];
+              S->stage.h[S->stage.cursor++] = dd;
+            }
+            if (is.cnt > 0) {
+              segs.push_back(sg);
+              cnt += is.cnt;
+            }
+          }
+          ++g;
+        }
+        if (members.empty()) continue;
+        if (cnt > 0) {
+          if (!h16_launch_ok(S->stage.h + from, cnt, h16 != 0)) {
+            g_last_error = "inner-solve descriptors do not match the launch's spectrum precision";
+            return FFTH_ERR_INVALID;
+          }
+          const Desc* d;
+          ffth_status s;
+          if ((s = stage_upload(m, S->stage, from, cnt, &d)) != FFTH_OK) return s;
+          // segment tables per pass, MULTI_SEGS grids per launch; each load's
+          // blocks are padded to a multiple of the 8 XCDs
+          std::vector<std::array<MultiSegs, 3>> tabs;
+          for (size_t c0 = 0; c0 < segs.size(); c0 += MULTI_SEGS) {
+            std::array<MultiSegs, 3> t;
+            for (int pass = 0; pass < 3; ++pass) {
+              MultiSegs& ms = t[pass];
+              std::memset(&ms, 0, sizeof(ms));
+              for (size_t c = c0; c < segs.size() && c < c0 + MULTI_SEGS; ++c) {
+                const int k = ms.n++;
+                ms.first[k] = segs[c].first;
+                ms.bpd[k] = segs[c].nb[pass];
+                ms.off[k + 1] = ms.off[k] + segs[c].count * ((segs[c].nb[pass] + 7) / 8 * 8);
+              }
+            }
+            tabs.push_back(t);
+          }
+          for (int j = 0; j < kmin; ++j) {
+            for (auto& t : tabs) HIPCHK(multi_ypass(t[0], m, d, -1, h16 != 0));
+            for (auto& t : tabs) HIPCHK(multi_zpass(t[1], m, d, OP_GAMMA, h16 != 0));
+            // the inverse y-transform reads the FP32 copy of a binary16 inner solve
+            for (auto& t : tabs) HIPCHK(multi_ypass(t[0], m, d, +1, false));
+            for (auto& t : tabs) HIPCHK(multi_xcg3(t[2], m, d, iso != 0, h16 != 0));
+            HIPCHK(launch_finalize(cnt, m, d, FIN_CG3, 0, -1));
+          }
+          S->multi_iterations += kmin;
+          S->multi_max_grids = std::max(S->multi_max_grids, (int32_t)std::min<size_t>(segs.size(), MULTI_SEGS));
+        }
+        for (size_t gm : members) kin[gm] = kmin;
+        g = 0;
+        for (auto& kv : groups) {
+          if (std::find(members.begin(), members.end(), g++) == members.end()) continue;
+          for (Job* J : kv.second)
+            if (J->phase == PH_INNER)
+              HIPCHK(hipMemcpyAsync(J->P->h_state, J->P->d_state, J->P->L.nstate * sizeof(SolverState),
+                                    hipMemcpyDeviceToHost, m));
+        }
+      }
+    }
   }
   return FFTH_OK;
 }
@@ -2067,14 +2203,40 @@ ffth_status ffth_server_step(ffth_server* S, int32_t* running, int32_t* waiting)
   // group running jobs by grid, material kind and spectrum precision (the
   // launches of a group take the first job's kernels); every group's round is
   // queued on its grid's stream, then the step waits for all streams once
-  std::map<std::tuple<int, int, int, bool, bool>, std::vector<Job*>> groups;
+  // The inner iterations of grids in the multi-size set that share a stream
+  // are deferred and then run for those sizes together, one launch per pass
+  // (issue_merged).
+  GroupMap groups;
   for (Request* r : S->running)
     groups[std::make_tuple(r->n[0], r->n[1], r->n[2], r->iso, r->job.P->h16)].push_back(&r->job);
   S->stage.cursor = 0;
   std::vector<int> kin(groups.size(), 0);
+  std::vector<InnerSet> inner(groups.size());
+  // A group's inner iterations join a multi-size launch only when another
+  // group with inner iterations this step shares its stream, material kind
+  // and spectrum precision (a launch across grid sizes saves launches there;
+  // a grid alone on its stream keeps the per-size kernels, whose default
+  // tiles compute the same values).
+  const bool merge = S->opts.scheme == FFTH_CG;
+  std::map<std::tuple<hipStream_t, bool, bool>, int> sharing;
+  std::vector<bool> eligible(groups.size(), false);
   size_t gi = 0;
-  for (auto& kv : groups)
-    if ((st = group_issue(kv.second, S->stage, &kin[gi++])) != FFTH_OK) return st;
+  for (auto& kv : groups) {
+    const ffth_plan* P0 = kv.second[0]->P;
+    bool in = false;
+    for (const Job* J : kv.second) in = in || J->phase == PH_INNER;
+    eligible[gi] = merge && in && multi_grid(P0->n);
+    if (eligible[gi]) ++sharing[std::make_tuple(P0->stream, P0->iso, P0->h16)];
+    ++gi;
+  }
+  gi = 0;
+  for (auto& kv : groups) {
+    const ffth_plan* P0 = kv.second[0]->P;
+    const bool defer = eligible[gi] && sharing[std::make_tuple(P0->stream, P0->iso, P0->h16)] >= 2;
+    if ((st = group_issue(kv.second, S->stage, &kin[gi], defer ? &inner[gi] : nullptr)) != FFTH_OK) return st;
+    ++gi;
+  }
+  if (merge && (st = issue_merged(S, groups, inner, kin)) != FFTH_OK) return st;
   for (hipStream_t sm : S->streams) HIPCHK(hipStreamSynchronize(sm));
   gi = 0;
   for (auto& kv : groups)
@@ -2094,6 +2256,13 @@ ffth_status ffth_server_step(ffth_server* S, int32_t* running, int32_t* waiting)
   if ((st = admit(S)) != FFTH_OK) return st;
   if (running) *running = (int32_t)S->running.size();
   if (waiting) *waiting = (int32_t)S->waiting.size();
+  return FFTH_OK;
+}
+
+ffth_status ffth_server_stats(ffth_server* S, int64_t* multi_iterations, int32_t* multi_max_grids) {
+  if (!S || !multi_iterations || !multi_max_grids) return FFTH_ERR_INVALID;
+  *multi_iterations = S->multi_iterations;
+  *multi_max_grids = S->multi_max_grids;
   return FFTH_OK;
 }
 

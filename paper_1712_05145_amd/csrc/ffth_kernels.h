@@ -599,15 +599,14 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
 // (the pair x_{k+1}, x_k overwrites x_{k-1}, x_{k-2} in slots x, x1).  A solve
 // that stops after an even iteration forms its last x in k_cg3_finish.
 // ---------------------------------------------------------------------------
-template <typename T, int N2, bool ISO, int ROWS = xi_rows<T>(N2), int NTB = NT, typename S = C2<T>, int PLAN = 0>
-__global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, long rows_total, long nvox) {
+// Row block b of nblk (its partial sums go to slot k at part_i + k nblk + b);
+// z: ROWS * 3 * (N2 + N2/16) LDS elements, tw: N2.
+template <typename T, int N2, bool ISO, int ROWS, int NTB, typename S, int PLAN>
+__device__ __forceinline__ void xcg3_tile(const Desc& d, int b, int nblk, long rows_total, long nvox, C2<T>* z,
+                                          C2<T>* tw) {
   constexpr int RS = N2 + N2 / 16;
-  __shared__ C2<T> z[ROWS * 3 * RS];
-  __shared__ C2<T> tw[N2];
-  const Desc& d = descs[blockIdx.y];
-  if (!d.st->active) return;
   build_twiddles<T, N2, NTB>(tw);
-  const long row0 = (long)blockIdx.x * ROWS;
+  const long row0 = (long)b * ROWS;
   // binary16 inner solve: eta comes from the FP32 copy, tau goes out in binary16
   constexpr bool FULL = std::is_same<S, C2<T>>::value;
   S* spec = (S*)d.spec;
@@ -692,7 +691,16 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
   lds_fft<T, N2, ROWS * 3, NTB, 1, RS, false, true, -1, 1, PLAN>(z, tw);
   store_rows_r2c<T, N2, ROWS, NTB, S>(spec, z, row0, rows_total);
   double sums[3] = {acc0, acc1, acc2};
-  block_sums<3, NTB>(sums, d.part_i + blockIdx.x, gridDim.x);
+  block_sums<3, NTB>(sums, d.part_i + b, nblk);
+}
+
+template <typename T, int N2, bool ISO, int ROWS = xi_rows<T>(N2), int NTB = NT, typename S = C2<T>, int PLAN = 0>
+__global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, long rows_total, long nvox) {
+  __shared__ C2<T> z[ROWS * 3 * (N2 + N2 / 16)];
+  __shared__ C2<T> tw[N2];
+  const Desc& d = descs[blockIdx.y];
+  if (!d.st->active) return;
+  xcg3_tile<T, N2, ISO, ROWS, NTB, S, PLAN>(d, (int)blockIdx.x, (int)gridDim.x, rows_total, nvox, z, tw);
 }
 
 // Three-term CG: the last x of loads whose solve stopped after an even
@@ -823,15 +831,12 @@ __device__ __forceinline__ void ypass_body(S* base, int ncols, int c0, C2<T>* bu
   }
 }
 
-template <typename T, int N1, int CW = y_cols<T>(N1), int NTB = y_threads<T>(N1), bool REMAP = true,
-          int V = vec_width<T>(), typename S = C2<T>, int PLAN = 0>
-__global__ __launch_bounds__(NTB) void k_ypass(const Desc* __restrict__ descs, int dir, int ncols, int ntiles) {
-  __shared__ __attribute__((aligned(16))) C2<T> buf[N1 * CW];
-  __shared__ C2<T> tw[N1];
-  const Desc& d = descs[blockIdx.y];
-  if (!d.st->active) return;
+// Tile bid (plane i0 = bid / ntiles, columns from (bid % ntiles) CW) of one
+// load; buf: N1 * CW LDS elements (16-byte aligned), tw: N1.
+template <typename T, int N1, int CW, int NTB, int V, typename S, int PLAN>
+__device__ __forceinline__ void ypass_tile(const Desc& d, int bid, int dir, int ncols, int ntiles, C2<T>* buf,
+                                           C2<T>* tw) {
   build_twiddles<T, N1, NTB>(tw);
-  const int bid = REMAP ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const long i0 = bid / ntiles;
   const int c0 = (bid % ntiles) * CW;
   // binary16 inner solve (spec2 set only in its descriptors): the inverse
@@ -840,6 +845,17 @@ __global__ __launch_bounds__(NTB) void k_ypass(const Desc* __restrict__ descs, i
   S* base = (S*)(alt ? d.spec2 : d.spec) + i0 * N1 * (long)ncols + c0;
   if (dir < 0) ypass_body<T, N1, CW, NTB, -1, V, S, PLAN>(base, ncols, c0, buf, tw);
   else ypass_body<T, N1, CW, NTB, +1, V, S, PLAN>(base, ncols, c0, buf, tw);
+}
+
+template <typename T, int N1, int CW = y_cols<T>(N1), int NTB = y_threads<T>(N1), bool REMAP = true,
+          int V = vec_width<T>(), typename S = C2<T>, int PLAN = 0>
+__global__ __launch_bounds__(NTB) void k_ypass(const Desc* __restrict__ descs, int dir, int ncols, int ntiles) {
+  __shared__ __attribute__((aligned(16))) C2<T> buf[N1 * CW];
+  __shared__ C2<T> tw[N1];
+  const Desc& d = descs[blockIdx.y];
+  if (!d.st->active) return;
+  const int bid = REMAP ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  ypass_tile<T, N1, CW, NTB, V, S, PLAN>(d, bid, dir, ncols, ntiles, buf, tw);
 }
 
 // ---------------------------------------------------------------------------
@@ -913,20 +929,17 @@ __device__ __forceinline__ void spectral_op(int op, T (&in)[6][2], T (&out)[6][2
   }
 }
 
-template <typename T, int N0, int TK = z_cols<T>(N0), int NTB = NT, bool REMAP = true, int V = vec_width<T>(),
-          typename S = C2<T>, int PLAN = 0>
-__global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, int op, int n1, int h, double scale) {
+// Tile bid (chunk bid / bpc, columns from (bid % bpc) TK) of one load; buf:
+// N0 * 6 TK LDS elements (16-byte aligned), tw: N0.
+template <typename T, int N0, int TK, int NTB, int V, typename S, int PLAN>
+__device__ __forceinline__ void zpass_tile(const Desc& d, int bid, int op, int n1, int h, double scale, C2<T>* buf,
+                                           C2<T>* tw) {
   constexpr int W = TK * 6;
-  __shared__ __attribute__((aligned(16))) C2<T> buf[N0 * W];
-  __shared__ C2<T> tw[N0];
-  const Desc& d = descs[blockIdx.y];
-  if (!d.st->active) return;
   build_twiddles<T, N0, NTB>(tw);
   // columns (i1, k2 % kc) of one k2-chunk form a [N0][M][6] sub-array
   const int kc = kchunk(h);
   const long M = (long)n1 * kc;
   const int bpc = (int)((M + TK - 1) / TK);            // blocks per chunk
-  const int bid = REMAP ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int chunk = bid / bpc;
   const long m0 = (long)(bid % bpc) * TK;
   constexpr bool FULL = std::is_same<S, C2<T>>::value;
@@ -1024,6 +1037,147 @@ __global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, i
         __builtin_nontemporal_store(o, (f4*)(dst + ((long)i0 * M + m0) * 6 + w));
       }
     }
+  }
+}
+
+template <typename T, int N0, int TK = z_cols<T>(N0), int NTB = NT, bool REMAP = true, int V = vec_width<T>(),
+          typename S = C2<T>, int PLAN = 0>
+__global__ __launch_bounds__(NTB) void k_zpass(const Desc* __restrict__ descs, int op, int n1, int h, double scale) {
+  __shared__ __attribute__((aligned(16))) C2<T> buf[N0 * TK * 6];
+  __shared__ C2<T> tw[N0];
+  const Desc& d = descs[blockIdx.y];
+  if (!d.st->active) return;
+  const int bid = REMAP ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
+  zpass_tile<T, N0, TK, NTB, V, S, PLAN>(d, bid, op, n1, h, scale, buf, tw);
+}
+
+// ---------------------------------------------------------------------------
+// Multi-size launches of the FP32 inner iteration: one launch per pass
+// covers loads of grids of different sizes (axis lengths from
+// FFTH_MULTI_SIZES).  Each load's descriptor carries its grid (n); the
+// launch's blocks are the tiles of all its loads, listed by a segment table
+// (MultiSegs) of consecutive loads of one grid, each tile with the default
+// tile shape of its lengths (variant 0, radix plan 0, 256 threads: the
+// arithmetic of the per-size kernels with their default tiles, bit for bit).
+// LDS is sized for the largest length.
+// ---------------------------------------------------------------------------
+#define FFTH_MULTI_SIZES(X) X(16) X(24) X(32) X(48) X(64) X(96) X(128)
+constexpr int MULTI_NT = 256;
+constexpr int MULTI_MAXN = 128;
+constexpr int MULTI_SIZES[] = {16, 24, 32, 48, 64, 96, 128};   // the lengths of FFTH_MULTI_SIZES
+constexpr bool multi_size(int n) {
+  for (int m : MULTI_SIZES)
+    if (m == n) return true;
+  return false;
+}
+#define FFTH_MULTI_CHECK(N) static_assert(multi_size(N), "FFTH_MULTI_SIZES and MULTI_SIZES differ");
+FFTH_MULTI_SIZES(FFTH_MULTI_CHECK)
+#undef FFTH_MULTI_CHECK
+#define FFTH_MULTI_COUNT(N) +1
+static_assert(0 FFTH_MULTI_SIZES(FFTH_MULTI_COUNT) == sizeof(MULTI_SIZES) / sizeof(int), "FFTH_MULTI_SIZES and MULTI_SIZES differ");
+#undef FFTH_MULTI_COUNT
+// blocks of one load of grid n in each multi-size pass (host and device)
+__host__ __device__ constexpr int multi_y_blocks(int n0, int n1, int n2) {
+  const int h = n2 / 2, kc = kchunk(h), cw = y_cols<float>(n1);
+  return n0 * (h / kc) * ((kc * 6 + cw - 1) / cw);
+}
+__host__ __device__ constexpr int multi_z_blocks(int n0, int n1, int n2) {
+  const int h = n2 / 2, kc = kchunk(h), tk = z_cols<float>(n0);
+  return (int)(((long)n1 * kc + tk - 1) / tk) * (h / kc);
+}
+__host__ __device__ constexpr int multi_x_blocks(int n0, int n1, int n2) {
+  const int r = xi_rows<float>(n2);
+  return (int)(((long)n0 * n1 + r - 1) / r);
+}
+// FP32 LDS elements of each pass at length n, and their maxima over the set
+constexpr int multi_lds(int pass, int n) {
+  return pass == 0 ? n * y_cols<float>(n) : pass == 1 ? n * 6 * z_cols<float>(n) : xi_rows<float>(n) * 3 * (n + n / 16);
+}
+constexpr int multi_lds_max(int pass) {
+  int m = 0;
+  for (int n : MULTI_SIZES) m = multi_lds(pass, n) > m ? multi_lds(pass, n) : m;
+  return m;
+}
+constexpr int MULTI_LDS_Y = multi_lds_max(0), MULTI_LDS_Z = multi_lds_max(1), MULTI_LDS_X = multi_lds_max(2);
+
+// Block of a multi-size launch: its load (descriptor index, -1 for padding)
+// and that load's tile.  Each load of segment s owns bpd[s] blocks padded to
+// a multiple of 8 (the XCDs; segments start at multiples of 8 too), so a
+// block's XCD is its tile slot mod 8; with REMAP the tiles of every load are
+// renumbered XCD-aware as the per-size y and z passes do (each XCD walks a
+// contiguous run of each load's tiles), without it a load's tiles are taken
+// in order as in the per-size fused pass.
+template <bool REMAP> __device__ __forceinline__ int multi_block(const MultiSegs& sg, int& tile) {
+  const int b = blockIdx.x;
+  int s = 0;
+  while (s + 1 < sg.n && b >= sg.off[s + 1]) ++s;
+  const int bpd = sg.bpd[s], slots = (bpd + 7) / 8 * 8;
+  const int r = b - sg.off[s], load = r / slots, t = r % slots;
+  if (t >= bpd) return -1;
+  tile = REMAP ? xcd_tile(t, bpd) : t;
+  return sg.first[s] + load;
+}
+template <typename S>
+__global__ __launch_bounds__(MULTI_NT) void k_ypass_multi(const Desc* __restrict__ descs, int dir, MultiSegs sg) {
+  __shared__ __attribute__((aligned(16))) C2<float> buf[MULTI_LDS_Y];
+  __shared__ C2<float> tw[MULTI_MAXN];
+  int bid;
+  const int di = multi_block<true>(sg, bid);
+  if (di < 0) return;
+  const Desc& d = descs[di];
+  if (!d.st->active) return;
+  const int kc = kchunk(d.n[2] / 2), ncols = kc * 6;
+  switch (d.n[1]) {
+#define FFTH_MULTI_Y(N)                                                                                   \
+  case N: {                                                                                               \
+    constexpr int CW = y_cols<float>(N);                                                                  \
+    ypass_tile<float, N, CW, MULTI_NT, 1, S, 0>(d, bid, dir, ncols, (ncols + CW - 1) / CW, buf, tw);    \
+    break;                                                                                                \
+  }
+    FFTH_MULTI_SIZES(FFTH_MULTI_Y)
+#undef FFTH_MULTI_Y
+  }
+}
+
+template <typename S>
+__global__ __launch_bounds__(MULTI_NT) void k_zpass_multi(const Desc* __restrict__ descs, int op, MultiSegs sg) {
+  __shared__ __attribute__((aligned(16))) C2<float> buf[MULTI_LDS_Z];
+  __shared__ C2<float> tw[MULTI_MAXN];
+  int bid;
+  const int di = multi_block<true>(sg, bid);
+  if (di < 0) return;
+  const Desc& d = descs[di];
+  if (!d.st->active) return;
+  switch (d.n[0]) {
+#define FFTH_MULTI_Z(N)                                                                                   \
+  case N:                                                                                                 \
+    zpass_tile<float, N, z_cols<float>(N), MULTI_NT, 1, S, 0>(d, bid, op, d.n[1], d.n[2] / 2, d.inv_nvox, buf, tw); \
+    break;
+    FFTH_MULTI_SIZES(FFTH_MULTI_Z)
+#undef FFTH_MULTI_Z
+  }
+}
+
+// The tile of the fused pass is the load's row block b, whose partial sums
+// go to slot b of the load's array.
+template <bool ISO, typename S>
+__global__ __launch_bounds__(MULTI_NT) void k_xcg3_multi(const Desc* __restrict__ descs, MultiSegs sg) {
+  __shared__ C2<float> z[MULTI_LDS_X];
+  __shared__ C2<float> tw[MULTI_MAXN];
+  int b;
+  const int di = multi_block<false>(sg, b);
+  if (di < 0) return;
+  const Desc& d = descs[di];
+  if (!d.st->active) return;
+  const int nb = multi_x_blocks(d.n[0], d.n[1], d.n[2]);
+  const long rows = (long)d.n[0] * d.n[1];
+  switch (d.n[2]) {
+#define FFTH_MULTI_X(N)                                                                                   \
+  case N:                                                                                                 \
+    xcg3_tile<float, N, ISO, xi_rows<float>(N), MULTI_NT, S, 0>(d, b, nb, rows, rows * N, z, tw);        \
+    break;
+    FFTH_MULTI_SIZES(FFTH_MULTI_X)
+#undef FFTH_MULTI_X
   }
 }
 

@@ -72,6 +72,7 @@ __global__ __launch_bounds__(NT_FIN) void k_finalize(const Desc* __restrict__ de
   const Desc& d = descs[blockIdx.x];
   SolverState* st = d.st;
   if (!st->active) return;
+  if (nblk_i < 0) nblk_i = d.nblk_multi;   // multi-size launch: each entry's own block count
   __shared__ double sf[NRED], si[NRED];
   int nf, ni;
   fin_slots(op, nf, ni);

@@ -43,7 +43,21 @@ template <typename T> struct Launch {
 
 
 // non-templated kernels (ffth_kernels_common.hip)
+// nblk_i < 0: each entry's own count (Desc::nblk_multi, after a multi-size fused pass)
 hipError_t launch_finalize(int nbatch, hipStream_t s, const Desc* d, int op, int nblk_f, int nblk_i);
+
+// Multi-size launches of the FP32 inner iteration (ffth_kernels_multi.hip)
+// for grids whose three axis lengths are all in the multi-size set (16, 24,
+// 32, 48, 64, 96, 128): one launch per pass over loads of different grids,
+// each descriptor carrying its grid (n) and, for the finalize, the block count
+// of its fused pass (nblk_multi).  The launch's blocks are listed by the
+// segment table sg (one grid per segment, at most MULTI_SEGS; bpd from
+// multi_blocks: y, z, fused x blocks per load), grid = sg.off[sg.n] blocks.
+bool multi_grid(const int n[3]);
+void multi_blocks(const int n[3], int out[3]);
+hipError_t multi_ypass(const MultiSegs& sg, hipStream_t s, const Desc* d, int dir, bool h16);
+hipError_t multi_zpass(const MultiSegs& sg, hipStream_t s, const Desc* d, int op, bool h16);
+hipError_t multi_xcg3(const MultiSegs& sg, hipStream_t s, const Desc* d, bool iso, bool h16);
 hipError_t launch_mean_stress(bool iso, int nblk, int nbatch, hipStream_t s, const Desc* d, long nvox);
 hipError_t launch_order1_point(bool iso, int nblk, int nbatch, hipStream_t s, const Desc* d, const double* eps0,
                                const double* x1, long nvox);

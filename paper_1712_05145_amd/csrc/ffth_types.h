@@ -81,7 +81,8 @@ struct Desc {
   int32_t h16;             // the inner solve keeps its spectrum in binary16
   int32_t nc_out;          // components of out written by the store / accumulate x-pass (0: nc)
   int32_t delta_gate;      // delta is the three-term inner solve's x: absent while it has no iteration
-  int32_t pad;
+  int32_t n[3];            // grid of this entry (multi-size launches)
+  int32_t nblk_multi;         // partial-sum blocks of its multi-size fused pass (finalize with nblk_i < 0)
 };
 
 // x-pass (forward) modes
@@ -97,6 +98,18 @@ enum : int32_t {
   FIN_LS_FIRST = 0, FIN_BS = 1, FIN_RESID_INIT = 2, FIN_CG_ALPHA = 3, FIN_CG_BETA = 4,
   FIN_OUTER = 5, FIN_SUMS_I = 6, FIN_O1RHS = 7, FIN_OUTER_P = 8, FIN_PROJ = 9, FIN_CG3_INIT = 10, FIN_CG3 = 11,
   FIN_BI_INIT = 12, FIN_BI_ALPHA = 13, FIN_BI_OMEGA = 14
+};
+
+// Block list of a multi-size launch: loads of one grid form a segment of
+// consecutive descriptors (first .. first + count - 1), each taking bpd
+// blocks padded to a multiple of 8 (the XCDs); segment s owns the launch's
+// blocks [off[s], off[s + 1]).
+constexpr int MULTI_SEGS = 16;
+struct MultiSegs {
+  int32_t n;
+  int32_t first[MULTI_SEGS];
+  int32_t bpd[MULTI_SEGS];
+  int32_t off[MULTI_SEGS + 1];
 };
 
 constexpr int NRED = 8;   // doubles per block in the partial-sum arrays

@@ -112,6 +112,8 @@ SIGNATURES = [
     ("ffth_poll", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ffth_result)]),
     ("ffth_cancel", ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     ("ffth_server_destroy", ctypes.c_int, [ctypes.c_void_p]),
+    ("ffth_server_stats", ctypes.c_int,
+     [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int32)]),
     ("ffth_green_apply_noalloc", ctypes.c_int,
      [ctypes.POINTER(ctypes.c_int32), ctypes.c_double, ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
       ctypes.c_int32, ctypes.c_void_p]),
@@ -506,6 +508,13 @@ def ffth_poll(srv, rid, nloads):
 
 def ffth_cancel(srv, rid):
     _check(load().ffth_cancel(srv, rid), "ffth_cancel")
+
+
+def ffth_server_stats(srv):
+    it = ctypes.c_int64()
+    grids = ctypes.c_int32()
+    _check(load().ffth_server_stats(srv, ctypes.byref(it), ctypes.byref(grids)), "ffth_server_stats")
+    return {"multi_iterations": it.value, "multi_max_grids": grids.value}
 
 
 def ffth_server_destroy(srv):

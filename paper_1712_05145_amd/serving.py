@@ -59,6 +59,11 @@ class Server:
             self.live.pop(rid, None)
         return st, res
 
+    def stats(self):
+        """Inner iterations run as multi-size launches and the most distinct
+        grids one such launch carried."""
+        return ffth.ffth_server_stats(self.srv)
+
     def cancel(self, rid):
         ffth.ffth_cancel(self.srv, rid)
 

@@ -44,9 +44,13 @@ def test_alone_equals_mix_and_plan_path():
     """Requests that share launches give bit-identical results alone and in
     the mix: a and b (128^3, stiffness contrast within the binary16 limit)
     share every binary16 launch; c and e (64^3, FP32 spectrum) share every
-    launch of their group.  d shares the 128^3 grid but is above the contrast
-    limit, so the server runs it in a separate launch group; the 48^3 request
-    runs alone in its group.  a is also identical through the plan path."""
+    launch of their group; d (128^3, above the contrast limit, so FP32
+    spectrum), f (48^3), g (32^3) and h (16^3) have groups of their own.  The
+    five grids take the server's four streams in order of admission, so h
+    shares the stream of c and e, and their inner iterations run as one
+    launch per pass across the two grid sizes.  a and c are also identical
+    through the plan path with autotuning off (the server keeps the default
+    tiles on grids of its multi-size launches)."""
     torch = require_gpu()
     from paper_1712_05145_amd.serving import Server
     a = _req(128, 0.25, 20.0, 1)
@@ -55,16 +59,21 @@ def test_alone_equals_mix_and_plan_path():
     d = _req(128, 0.35, 400.0, 4)
     e = _req(64, 0.1, 5.0, 5)
     f = _req(48, 0.2, 10.0, 3)
+    g = _req(32, 0.25, 30.0, 7)
+    h = _req(16, 0.3, 15.0, 8)
     lim = ffth.SPECTRUM16_MAX_CONTRAST
     assert ffth.ffth_stiffness_contrast(lame=a[1]) <= lim and ffth.ffth_stiffness_contrast(lame=b[1]) <= lim
     assert ffth.ffth_stiffness_contrast(lame=d[1]) > lim
-    shared = {"a": a, "b": b, "c": c, "e": e}
+    shared = {"a": a, "b": b, "c": c, "d": d, "e": e, "f": f, "g": g, "h": h}
     alone = {k: _alone(r) for k, r in shared.items()}
     s2 = Server(16 << 30, max_running=8)
-    order = [("c", c), ("f", f), ("a", a), ("d", d), ("e", e), ("b", b)]
+    order = [("c", c), ("f", f), ("a", a), ("d", d), ("g", g), ("h", h), ("e", e), ("b", b)]
     ids = {k: s2.submit(*r, np.eye(6)) for k, r in order}
     mixed = _drain(s2, list(ids.values()))
+    stats = s2.stats()
     s2.close()
+    print("multi-size launches", stats, flush=True)
+    assert stats["multi_iterations"] > 0 and stats["multi_max_grids"] >= 2
     for k in shared:
         st_alone, ra = alone[k]
         st_mix, rm = mixed[ids[k]]
@@ -73,12 +82,14 @@ def test_alone_equals_mix_and_plan_path():
         assert np.array_equal(np.array([r["mean_stress"] for r in ra]), np.array([r["mean_stress"] for r in rm])), k
         assert [r["iters"] for r in ra] == [r["iters"] for r in rm], k
         assert [r["fp64_applications"] for r in ra] == [r["fp64_applications"] for r in rm], k
-    # and identical to the single-plan path
-    sol = ffth.Solver(a[0], a[2], a[3], lame=a[1], nloads=6, precision="mixed", tol=1e-8)
-    _, rp = sol.solve_order0(np.eye(6))
-    sol.close()
-    assert np.array_equal(np.array([r["mean_stress"] for r in rp]),
-                          np.array([r["mean_stress"] for r in alone["a"][1]]))
+    # and identical to the single-plan path with the default tiles
+    for k in ("a", "c"):
+        r = shared[k]
+        sol = ffth.Solver(r[0], r[2], r[3], lame=r[1], nloads=6, precision="mixed", tol=1e-8, autotune=False)
+        _, rp = sol.solve_order0(np.eye(6))
+        sol.close()
+        assert np.array_equal(np.array([x["mean_stress"] for x in rp]),
+                              np.array([x["mean_stress"] for x in alone[k][1]])), k
     for k, rid in ids.items():
         assert mixed[rid][0] == 0, k
         cm = np.array([r["mean_stress"] for r in mixed[rid][1]]).T
@@ -104,7 +115,7 @@ def test_budget_admission_cancel_and_oversize():
     assert all(done[i][0] == 0 for i in ids[:3]), [done[i][0] for i in ids[:3]]
     # each request, run after a cancelled one in reused arena memory, equals the plan path
     for r, rid in zip(reqs[:3], ids[:3]):
-        sol = ffth.Solver(r[0], r[2], r[3], lame=r[1], nloads=6, precision="mixed", tol=1e-8)
+        sol = ffth.Solver(r[0], r[2], r[3], lame=r[1], nloads=6, precision="mixed", tol=1e-8, autotune=False)
         _, rp = sol.solve_order0(np.eye(6))
         sol.close()
         assert np.array_equal(np.array([x["mean_stress"] for x in rp]),
@@ -128,3 +139,36 @@ def test_short_stream_replay_mixed_sizes():
     assert stats["requests"] == 16 and stats["failed"] == 0
     assert stats["latency_p99_ms"] >= stats["latency_p50_ms"] > 0
     print(stats)
+
+
+def test_multi_size_launch_matches_oracle():
+    """Requests of six grids, four of them non-cubic, on the server's four
+    streams: the first two grids share their stream with the last two, and
+    the inner iterations of each such pair run as one launch per pass across
+    the two sizes.  Each request against the oracle's effective stiffness (CG
+    to 1e-12): |dC_IJ| <= 1e-7 sqrt(C_II C_JJ)."""
+    torch = require_gpu()
+    from oracle import homogenization as H
+    from paper_1712_05145_amd.serving import Server
+    cases = []
+    for shape, seed in (((16, 16, 16), 1), ((16, 24, 32), 2), ((32, 16, 24), 3), ((24, 24, 24), 4),
+                        ((16, 32, 16), 5), ((24, 16, 48), 6)):
+        phase = M.random_phases(shape, 3, seed)
+        lame = M.lame_from_young([1.0, 8.0, 3.0], [0.3, 0.25, 0.35])
+        lam0, mu0 = M.midpoint_reference(lame)
+        prob = H.make_problem(phase, lam0, mu0, lame=lame)
+        ceff, _, _ = H.effective_stiffness(prob, "cg", tol=1e-12)
+        cases.append((phase, lame, lam0, mu0, ceff))
+    srv = Server(4 << 30, max_running=8, tol=1e-10)
+    ids = [srv.submit(c[0], c[1], c[2], c[3], np.eye(6)) for c in cases]
+    done = _drain(srv, list(ids))
+    stats = srv.stats()
+    srv.close()
+    print("multi-size launches", stats, flush=True)
+    assert stats["multi_max_grids"] == 2
+    for c, rid in zip(cases, ids):
+        st, res = done[rid]
+        assert st == 0
+        cg = np.array([r["mean_stress"] for r in res]).T
+        d = np.sqrt(np.outer(np.diag(c[4]), np.diag(c[4])))
+        assert np.all(np.abs(cg - c[4]) <= 1e-7 * d), np.abs(cg - c[4]).max()

@@ -101,8 +101,9 @@ BYTES = {
 
 
 def measured_traffic(cat):
-    """HBM bytes per load-launch of kernel category `cat` from the committed
-    counter summary, or None when the kernel sources changed since it was taken."""
+    """HBM bytes per algorithmic byte of kernel category `cat` from the
+    committed counter summary (FETCH_SIZE + WRITE_SIZE, calibrated on device
+    copies), or None when the kernel sources changed since it was taken."""
     import glob
     import hashlib
     h = hashlib.sha256()
@@ -115,7 +116,7 @@ def measured_traffic(cat):
     if f"source-hash: {h.hexdigest()[:16]}" not in txt:
         return None
     for line in txt.splitlines():
-        if line.startswith(f"traffic-bytes-per-load-launch {cat}:"):
+        if line.startswith(f"traffic-ratio {cat}:"):
             return float(line.split(":")[1])
     return None
 
@@ -639,13 +640,15 @@ def main():
     for c in ALG_CATEGORIES:
         if c in kernels and prof[c][2]:
             kernels[c]["alg_bytes_per_voxel_per_load"] = round(model[c] / (nvox * prof[c][2]), 2)
-    # the committed counters were taken with the binary16 forward spectrum
-    t_unit = measured_traffic(cat) if h16 else None
+    # the committed counters were taken with the binary16 forward spectrum:
+    # HBM bytes per algorithmic byte there, times this run's algorithmic
+    # bytes per launch
+    t_ratio = measured_traffic(cat) if h16 else None
     upl = units / max(launches, 1)
     roofline = {"bound": "hbm", "kernel": cat, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if t_unit is None else round(t_unit * upl),
-                "traffic_per_load_launch": t_unit, "alg_bytes_per_launch": round(bytes_total / max(launches, 1)),
+                "traffic": None if t_ratio is None else round(t_ratio * bytes_total / max(launches, 1)),
+                "traffic_ratio": t_ratio, "alg_bytes_per_launch": round(bytes_total / max(launches, 1)),
                 "alg_bytes_per_voxel_per_load": round(bytes_total / (nvox * max(units, 1)), 2),
                 "units_per_launch": round(upl, 3),
                 "avg_launch_ms": round(tot_ms / max(launches, 1), 4),

@@ -16,12 +16,12 @@ from . import ffth
 
 class Server:
     def __init__(self, budget_bytes, max_running=32, tol=1e-8, inner_tol=1e-3, check_every=8, max_iter=20000,
-                 device="cuda:0", stream=None):
+                 device="cuda:0", stream=None, spectrum16=True):
         import torch
         self.torch = torch
         self.device = torch.device(device)
         self.opts = ffth.make_opts("cg", "mixed", tol=tol, max_iter=max_iter, inner_tol=inner_tol,
-                                   check_every=check_every)
+                                   check_every=check_every, spectrum16=spectrum16)
         self.arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device=self.device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         self.srv = ffth.ffth_server_create(ffth._dptr(self.arena), int(budget_bytes), self.opts, max_running,
@@ -31,18 +31,24 @@ class Server:
     def request_bytes(self, n, nphases, nloads=6):
         return ffth.ffth_request_bytes(n, nphases, nloads, self.opts)
 
-    def submit(self, phase, lame, lam0, mu0, E):
+    def submit(self, phase, lame, lam0, mu0, E, voigt21=None):
+        """One request: phase ids on the grid, the phases' (lambda, mu) pairs
+        (lame) or, with lame None, their 21 Voigt coefficients (voigt21)."""
         torch = self.torch
         ph = phase if not isinstance(phase, np.ndarray) else torch.from_numpy(
             np.ascontiguousarray(phase.astype(np.uint16)).view(np.int16))
         ph = ph.to(self.device).contiguous()
-        lame_a, lame_p = ffth._darr(lame)
         pr = ffth.ffth_problem()
         pr.n = (ctypes.c_int32 * 3)(*ph.shape)
-        pr.nphases = lame_a.reshape(-1, 2).shape[0]
+        if lame is not None:
+            lame_a, lame_p = ffth._darr(lame)
+            pr.nphases = lame_a.reshape(-1, 2).shape[0]
+            pr.lame, pr.stiffness = lame_p, None
+        else:
+            lame_a, v_p = ffth._darr(np.asarray(voigt21, np.float64).reshape(-1, 21))
+            pr.nphases = lame_a.shape[0]
+            pr.lame, pr.stiffness = None, v_p
         pr.phase = ph.data_ptr()
-        pr.lame = lame_p
-        pr.stiffness = None
         pr.lambda0, pr.mu0 = lam0, mu0
         E = np.asarray(E, np.float64).reshape(-1, 6)
         rid = ffth.ffth_submit(self.srv, pr, E)

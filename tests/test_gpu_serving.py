@@ -172,3 +172,46 @@ def test_multi_size_launch_matches_oracle():
         cg = np.array([r["mean_stress"] for r in res]).T
         d = np.sqrt(np.outer(np.diag(c[4]), np.diag(c[4])))
         assert np.all(np.abs(cg - c[4]) <= 1e-7 * d), np.abs(cg - c[4]).max()
+
+
+def test_multi_size_binary16_and_anisotropic_match_oracle():
+    """Binary16 spectrum forced on small grids, isotropic and anisotropic
+    phases: five grids on the server's four streams, so the first and the last
+    share a stream and their inner iterations run as one binary16 launch per
+    pass across the two sizes (for each material kind).  Every request against
+    the oracle's effective stiffness (CG to 1e-12): |dC_IJ| <= 1e-7
+    sqrt(C_II C_JJ)."""
+    torch = require_gpu()
+    from oracle import homogenization as H
+    from paper_1712_05145_amd.serving import Server
+    rng = np.random.default_rng(21)
+    v21 = []
+    for _ in range(3):
+        a = rng.standard_normal((6, 6))
+        c = a @ a.T + 6 * np.eye(6)
+        v21.append([c[i, j] for i in range(6) for j in range(i, 6)])
+    v21 = np.array(v21)
+    lame = M.lame_from_young([1.0, 6.0, 2.5], [0.3, 0.25, 0.35])
+    assert ffth.ffth_stiffness_contrast(voigt21=v21) <= ffth.SPECTRUM16_MAX_CONTRAST
+    assert ffth.ffth_stiffness_contrast(lame=lame) <= ffth.SPECTRUM16_MAX_CONTRAST
+    cases = []
+    for i, shape in enumerate(((16, 16, 16), (24, 16, 16), (16, 24, 16), (16, 16, 24), (16, 32, 16))):
+        phase = M.random_phases(shape, 3, 30 + i)
+        lam0, mu0 = M.midpoint_reference(lame)
+        ce, _, _ = H.effective_stiffness(H.make_problem(phase, lam0, mu0, lame=lame), "cg", tol=1e-12)
+        cases.append((phase, lame, None, lam0, mu0, ce))
+        ce, _, _ = H.effective_stiffness(H.make_problem(phase, 3.0, 3.0, voigt21=v21), "cg", tol=1e-12)
+        cases.append((phase, None, v21, 3.0, 3.0, ce))
+    srv = Server(4 << 30, max_running=16, tol=1e-10, spectrum16="force")
+    ids = [srv.submit(c[0], c[1], c[3], c[4], np.eye(6), voigt21=c[2]) for c in cases]
+    done = _drain(srv, list(ids))
+    stats = srv.stats()
+    srv.close()
+    print("multi-size launches", stats, flush=True)
+    assert stats["multi_max_grids"] == 2
+    for c, rid in zip(cases, ids):
+        st, res = done[rid]
+        assert st == 0
+        cg = np.array([r["mean_stress"] for r in res]).T
+        d = np.sqrt(np.outer(np.diag(c[5]), np.diag(c[5])))
+        assert np.all(np.abs(cg - c[5]) <= 1e-7 * d), np.abs(cg - c[5]).max()

@@ -191,3 +191,10 @@ def test_launch_loads_need_a_plan():
     arr = (ctypes.c_int32 * 2)(1, 1)
     assert lib.ffth_launch_loads(None, arr) == ffth.FFTH_ERR_INVALID
     assert lib.ffth_set_launch_loads(None, arr) == ffth.FFTH_ERR_INVALID
+
+
+def test_server_stats_need_a_server():
+    """The multi-size launch counters refuse a null server (no GPU)."""
+    lib = ffth.load()
+    it, grids = ctypes.c_int64(), ctypes.c_int32()
+    assert lib.ffth_server_stats(None, ctypes.byref(it), ctypes.byref(grids)) == ffth.FFTH_ERR_INVALID

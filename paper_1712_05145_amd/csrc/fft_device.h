@@ -258,13 +258,36 @@ __device__ __forceinline__ void fft_stage(C2<T>* buf, const C2<T>* tw) {
       const int j = FFAST ? it / NG : it % NB;
       const C2<T>* src = buf + g * V * FS;
       const int kk = j % NS;
+      // radix 16: the twiddles w^r, r = 1..15, from w, w^2, w^4, w^8 (four
+      // table reads) by at most three products each
+      constexpr bool POW = R == 16;
+      C2<T> wp[4];
+      if constexpr (POW && NS > 1) {
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          wp[b] = tw[(1 << b) * kk * (N / (NS * R))];
+          if (DIR > 0) wp[b].y = -wp[b].y;
+        }
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         C2<T> a[V];
         load_v<T, V>(src + padx<PADDED>((j + r * NB) * ES), a);
         if (NS > 1 && r > 0) {
-          C2<T> w = tw[r * kk * (N / (NS * R))];
-          if (DIR > 0) w.y = -w.y;
+          C2<T> w;
+          if constexpr (POW) {
+            bool have = false;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              if (r & (1 << b)) {
+                w = have ? cmul(w, wp[b]) : wp[b];
+                have = true;
+              }
+            }
+          } else {
+            w = tw[r * kk * (N / (NS * R))];
+            if (DIR > 0) w.y = -w.y;
+          }
 #pragma unroll
           for (int q = 0; q < V; ++q) a[q] = cmul(a[q], w);
         }

@@ -258,13 +258,14 @@ __device__ __forceinline__ void fft_stage(C2<T>* buf, const C2<T>* tw) {
       const int j = FFAST ? it / NG : it % NB;
       const C2<T>* src = buf + g * V * FS;
       const int kk = j % NS;
-      // radix 16: the twiddles w^r, r = 1..15, from w, w^2, w^4, w^8 (four
-      // table reads) by at most three products each
-      constexpr bool POW = R == 16;
-      C2<T> wp[4];
+      // radix 4, 8, 16: the twiddles w^r, r = 1..R-1, from w, w^2, w^4, ...
+      // (log2 R table reads) by at most log2 R - 1 products each
+      constexpr int LB = R == 16 ? 4 : R == 8 ? 3 : R == 4 ? 2 : 0;
+      constexpr bool POW = LB > 0;
+      C2<T> wp[LB > 0 ? LB : 1];
       if constexpr (POW && NS > 1) {
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < LB; ++b) {
           wp[b] = tw[(1 << b) * kk * (N / (NS * R))];
           if (DIR > 0) wp[b].y = -wp[b].y;
         }
@@ -278,7 +279,7 @@ __device__ __forceinline__ void fft_stage(C2<T>* buf, const C2<T>* tw) {
           if constexpr (POW) {
             bool have = false;
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
+            for (int b = 0; b < LB; ++b) {
               if (r & (1 << b)) {
                 w = have ? cmul(w, wp[b]) : wp[b];
                 have = true;

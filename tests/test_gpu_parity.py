@@ -343,7 +343,8 @@ def test_every_tile_variant_solve_parity(sphere16_oracle, variant, scheme):
 
 
 @pytest.mark.parametrize("scheme,precision", [("cg", "mixed"), ("basic", "mixed"), ("cg", "fp64"),
-                                              ("bicgstab", "fp64"), ("cg3", "fp64"), ("cg3", "fp32")])
+                                              ("bicgstab", "fp64"), ("cg3", "fp64"), ("cg3", "fp32"),
+                                              ("cg", "mixed-binary16")])
 def test_loads_per_launch_bit_identical(sphere16_oracle, scheme, precision):
     """Loads taken one and four at a time through every pass of an iteration
     (load-major order) give the results of one launch per pass bit for bit:
@@ -353,10 +354,12 @@ def test_loads_per_launch_bit_identical(sphere16_oracle, scheme, precision):
     print("case launch loads", scheme, precision, flush=True)
     phase, lame, lam0, mu0, ceff, corr, _ = sphere16_oracle
     tol = 1e-5 if precision == "fp32" else 1e-10
+    h16 = precision == "mixed-binary16"      # the binary16 spectrum forced on this small grid
+    prec = "mixed" if h16 else precision
     out = {}
     for w in (0, 1, 4):
-        s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, scheme=scheme, precision=precision, tol=tol,
-                        max_iter=5000, autotune=False)
+        s = ffth.Solver(phase, lam0, mu0, lame=lame, nloads=6, scheme=scheme, precision=prec, tol=tol,
+                        max_iter=5000, autotune=False, spectrum16="force" if h16 else True)
         s.launch_loads = [w, w]
         assert s.launch_loads == [w, w]
         eps, res = s.solve_order0(np.eye(6))

@@ -706,8 +706,9 @@ __global__ __launch_bounds__(NTB) void k_xcg3(const Desc* __restrict__ descs, lo
 // Three-term CG: the last x of loads whose solve stopped after an even
 // iteration k (their state says so).  The odd iteration k - 1 left x_k and
 // x_{k-1} in the slots x and x1; x_{k+1} = omega_k (x_k + gamma_k r_k) +
-// (1 - omega_k) x_{k-1} goes to x, x_k to x1 (k = 0: x_1 = gamma_0 r_0).
-// n = 6 x voxels.  Run once per stopped solve (the update is not idempotent).
+// (1 - omega_k) x_{k-1} goes to x (k = 0: x_1 = gamma_0 r_0); nothing reads
+// x1 after a solve, so it is left as it is.  n = 6 x voxels.  Run once per
+// stopped solve (the update is not idempotent).
 template <typename T>
 __global__ __launch_bounds__(NT) void k_cg3_finish(const Desc* __restrict__ descs, long n) {
   const Desc& d = descs[blockIdx.y];
@@ -718,14 +719,13 @@ __global__ __launch_bounds__(NT) void k_cg3_finish(const Desc* __restrict__ desc
   const T om = k == 0 ? T(1) : (T)st->beta;
   const T* rk = (const T*)rslot(d, k);
   T* xn = (T*)d.x;
-  T* xo = (T*)d.x1;
+  const T* xo = (const T*)d.x1;
   for (long i = (long)blockIdx.x * NT + threadIdx.x; i < n; i += (long)gridDim.x * NT) {
     if (k == 0) {
       xn[i] = gam * rk[i];
     } else {
       const T xa = xn[i], xb = xo[i];
       xn[i] = om * (xa + gam * rk[i]) + (T(1) - om) * xb;
-      xo[i] = xa;
     }
   }
 }

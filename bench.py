@@ -72,13 +72,15 @@ BYTES = {
     # application: spectrum read and written
     "y64": 2 * F64, "z64": 2 * F64,
     # FP64 residual sweep of the defect correction (x-forward, mode LS): the
-    # first sweep reads the iterate (zero) and ids and writes the spectrum;
-    # later sweeps also read the FP32 correction and write the iterate back;
-    # order 1 also reads the stored right-hand-side polarization
-    "sweep0_xf": IDB + F64 + F64, "sweep_xf": IDB + F64 + F32W + F64 + F64, "rhs_P": F64,
+    # first sweep reads ids and writes the spectrum (the iterate is zero and
+    # not read); later sweeps also read the iterate and the FP32 correction
+    # and write the iterate back; order 1 also reads the stored
+    # right-hand-side polarization
+    "sweep0_xf": IDB + F64, "sweep_xf": IDB + F64 + F32W + F64 + F64, "rhs_P": F64,
     # its x-inverse (mode RESID): spectrum and iterate read, residual written
-    # (FP32 after the first sweep's, which goes straight to the inner solve)
-    "sweep0_xi": F64 + F64 + F32W, "sweep_xi": F64 + F64 + F64,
+    # (the first sweep reads no iterate and writes an FP32 residual, which
+    # goes straight to the inner solve)
+    "sweep0_xi": F64 + F32W, "sweep_xi": F64 + F64 + F64,
     # FP32 projection of the FP64 residual: x-forward (C0 : r) reads r (FP64)
     # and ids and writes the spectrum; y/z 48 each; x-inverse reads the
     # spectrum, x and r (FP64) and writes x (FP64) and the FP32 right-hand side

@@ -970,6 +970,8 @@ ffth_status group_issue(std::vector<Job*>& jobs, Stage& st, int* kin_out, InnerS
     for (Job* J : jobs)
       if (J->phase == ph) cnt[ph] += stage_append(st, *J, role[ph], 0);
   }
+  // the first sweep of a solve runs on the zero iterate: its passes skip reading it
+  for (int i = 0; i < cnt[PH_A0]; ++i) st.h[from[PH_A0] + i].x_zero = 1;
   // inner loads: those whose solve starts this round first (they take the start pass)
   from[3] = st.cursor;
   for (int pass = 0; pass < 2; ++pass) {

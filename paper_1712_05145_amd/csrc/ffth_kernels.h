@@ -271,7 +271,7 @@ __global__ __launch_bounds__(NTB) void k_xfwd(const Desc* __restrict__ descs, in
       const int ph = d.phase[vox];
       if (mode == XF_LS) {
         T x[6] = {0, 0, 0, 0, 0, 0};
-        T* xp = (T*)d.x;
+        T* xp = d.x_zero ? nullptr : (T*)d.x;
         if (xp) {
 #pragma unroll
           for (int c = 0; c < 6; ++c) x[c] = xp[c * nvox + vox];
@@ -471,7 +471,7 @@ __global__ __launch_bounds__(NTB) void k_xinv(const Desc* __restrict__ descs, in
       const T* xp = (const T*)d.x;
       double r[6];
 #pragma unroll
-      for (int c = 0; c < 6; ++c) r[c] = (double)eta[c] - (double)xp[c * nvox + vox];
+      for (int c = 0; c < 6; ++c) r[c] = (double)eta[c] - (d.x_zero ? 0.0 : (double)xp[c * nvox + vox]);
       if (d.r_f32) {
         float* rp = (float*)d.r;
 #pragma unroll

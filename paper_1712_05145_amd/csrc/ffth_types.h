@@ -82,7 +82,8 @@ struct Desc {
   int32_t nc_out;          // components of out written by the store / accumulate x-pass (0: nc)
   int32_t delta_gate;      // delta is the three-term inner solve's x: absent while it has no iteration
   int32_t n[3];            // grid of this entry (multi-size launches)
-  int32_t nblk_multi;         // partial-sum blocks of its multi-size fused pass (finalize with nblk_i < 0)
+  int32_t nblk_multi;      // partial-sum blocks of its multi-size fused pass (finalize with nblk_i < 0)
+  int32_t x_zero;          // the iterate x is zero (first residual sweep of a solve): not read
 };
 
 // x-pass (forward) modes

@@ -282,15 +282,16 @@ ffth_status ffth_set_launch_loads(ffth_plan *plan, const int32_t in[2]);
  * max_running slots is free: the waiting request of least work (voxels x
  * loads) whose memory (ffth_request_bytes) fits the free arena goes first
  * (ties: earlier arrival); a request passed over max_running times goes next
- * as soon as its memory fits, and nothing passes it meanwhile.  Each
- * ffth_server_step advances every running request by one phase of the
+ * as soon as its memory fits, and nothing passes it meanwhile.  A round
+ * advances every running request of a stream by one phase of the
  * mixed-precision solve (an FP64 residual sweep, the compatible projection,
  * or check_every FP32 iterations); requests of the same grid size, material
  * kind and spectrum precision share every kernel launch, and each grid size
  * is bound to one of four streams (the caller's and three the server
- * creates), so that sizes run concurrently; a step waits for all of them.  A completed request returns its
- * memory to the arena and its results (mean stresses, i.e. C_eff columns
- * for unit loads) to ffth_poll.  Results do not depend on what else runs:
+ * creates), so that sizes run concurrently, each stream at its own pace
+ * (ffth_server_step).  A completed request returns its memory to the arena
+ * and its results (mean stresses, i.e. C_eff columns for unit loads) to
+ * ffth_poll.  Results do not depend on what else runs:
  * every load keeps its own iteration state and reductions are fixed-order.
  *   arena: DEVICE, 256-byte aligned, caller-owned, outlives the server.
  *   opts:  precision must be FFTH_MIXED.
@@ -303,7 +304,14 @@ ffth_status ffth_server_create(ffth_server **out, void *arena, size_t arena_byte
 /* FFTH_ERR_OOM if the request can never fit the arena. */
 ffth_status ffth_submit(ffth_server *srv, const ffth_problem *p, int32_t nloads, const double *E,
                         uint64_t *request_id);
-/* One round; running / waiting (may be NULL) receive the queue sizes after it. */
+/* Advance the server.  Each of its streams runs rounds of its own (a round
+ * advances every running request on the stream by one phase step): the call
+ * admits what fits, starts a round on every idle stream that has running
+ * requests, and completes every round that has finished (phase transitions,
+ * finished requests, whose memory goes back to the arena) and starts that
+ * stream's next one; if no round has finished it waits for the oldest.  So
+ * small grids are not held to the pace of large ones.  running / waiting (may
+ * be NULL) receive the queue sizes after it. */
 ffth_status ffth_server_step(ffth_server *srv, int32_t *running, int32_t *waiting);
 /* FFTH_ERR_BUSY until complete; then the request's status, res[nloads] filled,
  * and the id is released.  FFTH_ERR_CANCELLED for cancelled requests. */

@@ -1908,7 +1908,20 @@ struct ffth_server {
   int max_bypass = 0;                      // admissions that may pass a waiting request
   int64_t multi_iterations = 0;            // inner iterations run as multi-size launches
   int32_t multi_max_grids = 0;             // most distinct grids in one multi-size launch
-  Stage stage{nullptr, nullptr, 0, 0};
+  // Each stream runs its own rounds: a round is issued on an idle stream, and
+  // completed (phase transitions, finished requests) once its event has
+  // passed, independently of the other streams.
+  struct Round {
+    bool busy = false;
+    uint64_t seq = 0;                      // issue order (the oldest busy round is waited for first)
+    hipEvent_t done = nullptr;             // recorded after the round's last command
+    std::vector<std::vector<Job*>> groups; // the round's launch groups
+    std::vector<int> kin;                  // inner iterations each group ran
+  };
+  std::vector<Round> rounds;               // per stream
+  std::vector<Stage> stages;               // descriptor staging per stream (a round's are in flight)
+  size_t stage_bytes = 0;                  // arena bytes of all streams' staging areas
+  uint64_t seq = 0;
   FreeList free_;                          // free ranges of the arena
   std::deque<Request*> waiting;
   std::vector<Request*> running;
@@ -1956,8 +1969,7 @@ ffth_status admit(ffth_server* S) {
     if (!S->free_.alloc(r->bytes, &off)) break;
     for (int i = 0; i < k; ++i) S->waiting[i]->bypassed++;
     S->waiting.erase(S->waiting.begin() + k);
-    const size_t stage_bytes = al((size_t)S->stage.cap * sizeof(Desc));
-    if (off < stage_bytes || off + r->bytes > S->bytes) {   // never place over the staging area
+    if (off < S->stage_bytes || off + r->bytes > S->bytes) {   // never place over the staging areas
       finish_request(S, r, FFTH_ERR_OOM);
       continue;
     }
@@ -2007,13 +2019,13 @@ using GroupMap = std::map<std::tuple<int, int, int, bool, bool>, std::vector<Job
 // the smallest of the iteration counts its groups asked for (kin updated);
 // the states of their jobs in the inner phase are read back after the last
 // iteration.
-ffth_status issue_merged(ffth_server* S, GroupMap& groups, const std::vector<InnerSet>& inner,
+ffth_status issue_merged(ffth_server* S, Stage& stage, GroupMap& groups, const std::vector<InnerSet>& inner,
                          std::vector<int>& kin) {
   size_t g = 0;
   for (hipStream_t m : S->streams) {
     for (int iso = 0; iso < 2; ++iso) {
       for (int h16 = 0; h16 < 2; ++h16) {
-        const int from = S->stage.cursor;
+        const int from = stage.cursor;
         int cnt = 0, kmin = INT32_MAX;
         struct Seg {
           int first, count, nb[3];
@@ -2027,16 +2039,16 @@ ffth_status issue_merged(ffth_server* S, GroupMap& groups, const std::vector<Inn
           if (is.deferred && P0->stream == m && P0->iso == (iso != 0) && P0->h16 == (h16 != 0)) {
             members.push_back(g);
             kmin = std::min(kmin, is.kin);
-            if (S->stage.cursor + is.cnt > S->stage.cap) {
+            if (stage.cursor + is.cnt > stage.cap) {
               g_last_error = "descriptor staging area too small for the step";
               return FFTH_ERR_INVALID;
             }
             Seg sg{cnt, is.cnt, {0, 0, 0}};
             multi_blocks(P0->n, sg.nb);
             for (int i = 0; i < is.cnt; ++i) {
-              Desc dd = S->stage.h[is.from + i];
+              Desc dd = stage.h[is.from + i];
               dd.nblk_multi = sg.nb[2];
-              S->stage.h[S->stage.cursor++] = dd;
+              stage.h[stage.cursor++] = dd;
             }
             if (is.cnt > 0) {
               segs.push_back(sg);
@@ -2047,13 +2059,13 @@ ffth_status issue_merged(ffth_server* S, GroupMap& groups, const std::vector<Inn
         }
         if (members.empty()) continue;
         if (cnt > 0) {
-          if (!h16_launch_ok(S->stage.h + from, cnt, h16 != 0)) {
+          if (!h16_launch_ok(stage.h + from, cnt, h16 != 0)) {
             g_last_error = "inner-solve descriptors do not match the launch's spectrum precision";
             return FFTH_ERR_INVALID;
           }
           const Desc* d;
           ffth_status s;
-          if ((s = stage_upload(m, S->stage, from, cnt, &d)) != FFTH_OK) return s;
+          if ((s = stage_upload(m, stage, from, cnt, &d)) != FFTH_OK) return s;
           // segment tables per pass, MULTI_SEGS grids per launch; each load's
           // blocks are padded to a multiple of the 8 XCDs
           std::vector<std::array<MultiSegs, 3>> tabs;
@@ -2097,6 +2109,88 @@ ffth_status issue_merged(ffth_server* S, GroupMap& groups, const std::vector<Inn
   return FFTH_OK;
 }
 
+// Issue the next round of stream k: every running request bound to it,
+// grouped by grid, material kind and spectrum precision (a group's launches
+// take its first job's kernels); the inner iterations of multi-size grids
+// that share the stream are deferred and run together, one launch per pass
+// across their sizes (issue_merged).  A group joins such a launch only when
+// another group with inner iterations in this round shares its material kind
+// and spectrum precision (a grid alone on the stream keeps the per-size
+// kernels, whose default tiles compute the same values).
+ffth_status issue_round(ffth_server* S, size_t k) {
+  ffth_server::Round& R = S->rounds[k];
+  hipStream_t sm = S->streams[k];
+  GroupMap groups;
+  for (Request* r : S->running)
+    if (r->P->stream == sm)
+      groups[std::make_tuple(r->n[0], r->n[1], r->n[2], r->iso, r->job.P->h16)].push_back(&r->job);
+  if (groups.empty()) return FFTH_OK;
+  Stage& stage = S->stages[k];
+  stage.cursor = 0;
+  std::vector<int> kin(groups.size(), 0);
+  std::vector<InnerSet> inner(groups.size());
+  const bool merge = S->opts.scheme == FFTH_CG;
+  std::map<std::tuple<bool, bool>, int> sharing;
+  std::vector<bool> eligible(groups.size(), false);
+  size_t gi = 0;
+  for (auto& kv : groups) {
+    const ffth_plan* P0 = kv.second[0]->P;
+    bool in = false;
+    for (const Job* J : kv.second) in = in || J->phase == PH_INNER;
+    eligible[gi] = merge && in && multi_grid(P0->n);
+    if (eligible[gi]) ++sharing[std::make_tuple(P0->iso, P0->h16)];
+    ++gi;
+  }
+  ffth_status st;
+  gi = 0;
+  for (auto& kv : groups) {
+    const ffth_plan* P0 = kv.second[0]->P;
+    const bool defer = eligible[gi] && sharing[std::make_tuple(P0->iso, P0->h16)] >= 2;
+    if ((st = group_issue(kv.second, stage, &kin[gi], defer ? &inner[gi] : nullptr)) != FFTH_OK) return st;
+    ++gi;
+  }
+  if (merge && (st = issue_merged(S, stage, groups, inner, kin)) != FFTH_OK) return st;
+  HIPCHK(hipEventRecord(R.done, sm));
+  R.busy = true;
+  R.seq = ++S->seq;
+  R.groups.clear();
+  for (auto& kv : groups) R.groups.push_back(kv.second);
+  R.kin = kin;
+  return FFTH_OK;
+}
+
+// Complete stream k's round once its event has passed: phase transitions of
+// its groups (their states were read back by the round), then the finished
+// requests on the stream (volume averages, results, memory back to the arena).
+ffth_status complete_round(ffth_server* S, size_t k) {
+  ffth_server::Round& R = S->rounds[k];
+  if (!R.busy) return FFTH_OK;
+  R.busy = false;
+  ffth_status st;
+  for (size_t g = 0; g < R.groups.size(); ++g)
+    if ((st = group_advance(R.groups[g], R.kin[g])) != FFTH_OK) return st;
+  R.groups.clear();
+  R.kin.clear();
+  std::vector<Request*> still;
+  for (Request* r : S->running) {
+    if (r->P->stream != S->streams[k] || r->job.phase != PH_DONE) {
+      still.push_back(r);
+      continue;
+    }
+    r->res.assign(r->nl, ffth_result{});
+    ffth_status fs = solve_finish(r->P, r->nl, r->eps, r->res.data(), r->t_submit, nullptr);
+    finish_request(S, r, fs);
+  }
+  S->running.swap(still);
+  return FFTH_OK;
+}
+
+size_t stream_index(const ffth_server* S, hipStream_t sm) {
+  for (size_t k = 0; k < S->streams.size(); ++k)
+    if (S->streams[k] == sm) return k;
+  return 0;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2120,9 +2214,12 @@ ffth_status ffth_server_create(ffth_server** out, void* arena, size_t arena_byte
     g_last_error = "arena must be 256-byte aligned; serving runs the mixed-precision solver";
     return FFTH_ERR_INVALID;
   }
-  // every running request has at most 6 loads, each staged at most twice per step
+  // every running request has at most 6 loads, each staged at most twice per
+  // round; any one stream may carry all of them, and the rounds of different
+  // streams are in flight together, so each stream has a staging area of its own
   const int cap = 12 * max_running;
-  const size_t stage_bytes = al((size_t)cap * sizeof(Desc));
+  const size_t one = al((size_t)cap * sizeof(Desc));
+  const size_t stage_bytes = one * FFTH_SERVER_STREAMS;
   if (arena_bytes <= stage_bytes) {
     g_last_error = "arena too small";
     return FFTH_ERR_OOM;
@@ -2134,24 +2231,31 @@ ffth_status ffth_server_create(ffth_server** out, void* arena, size_t arena_byte
   S->opts = *o;
   S->max_running = max_running;
   S->max_bypass = max_running;
-  S->stage.d = (Desc*)S->arena;
-  S->stage.cap = cap;
-  if (!hip_ok(hipHostMalloc((void**)&S->stage.h, (size_t)cap * sizeof(Desc), hipHostMallocDefault),
-              "hipHostMalloc")) {
-    delete S;
-    return FFTH_ERR_DEVICE;
+  S->stage_bytes = stage_bytes;
+  S->rounds.resize(FFTH_SERVER_STREAMS);
+  S->stages.assign(FFTH_SERVER_STREAMS, Stage{nullptr, nullptr, cap, 0});
+  bool ok = true;
+  for (int i = 0; i < FFTH_SERVER_STREAMS && ok; ++i) {
+    S->stages[i].d = (Desc*)(S->arena + (size_t)i * one);
+    ok = hip_ok(hipHostMalloc((void**)&S->stages[i].h, (size_t)cap * sizeof(Desc), hipHostMallocDefault),
+                "hipHostMalloc") &&
+         hip_ok(hipEventCreateWithFlags(&S->rounds[i].done, hipEventDisableTiming), "hipEventCreate");
   }
   S->streams.push_back(S->stream);
-  for (int i = 1; i < FFTH_SERVER_STREAMS; ++i) {
+  for (int i = 1; i < FFTH_SERVER_STREAMS && ok; ++i) {
     hipStream_t st;
     // default priority, no implicit synchronisation with the null stream
-    if (!hip_ok(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate")) {
-      for (size_t j = 1; j < S->streams.size(); ++j) (void)hipStreamDestroy(S->streams[j]);
-      (void)hipHostFree(S->stage.h);
-      delete S;
-      return FFTH_ERR_DEVICE;
-    }
-    S->streams.push_back(st);
+    ok = hip_ok(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
+    if (ok) S->streams.push_back(st);
+  }
+  if (!ok) {
+    for (size_t j = 1; j < S->streams.size(); ++j) (void)hipStreamDestroy(S->streams[j]);
+    for (auto& st : S->stages)
+      if (st.h) (void)hipHostFree(st.h);
+    for (auto& r : S->rounds)
+      if (r.done) (void)hipEventDestroy(r.done);
+    delete S;
+    return FFTH_ERR_DEVICE;
   }
   S->free_.reset(stage_bytes, arena_bytes - stage_bytes);
   *out = S;
@@ -2186,7 +2290,7 @@ ffth_status ffth_submit(ffth_server* S, const ffth_problem* p, int32_t nloads, c
   r->E.assign(E, E + 6 * nloads);
   r->bytes = request_bytes(r->n, p->nphases, nloads, S->opts, &r->ws_bytes);
   r->t_submit = now_s();
-  if (r->bytes > S->bytes - al((size_t)S->stage.cap * sizeof(Desc))) {
+  if (r->bytes > S->bytes - S->stage_bytes) {
     delete r;
     g_last_error = "request larger than the whole arena";
     return FFTH_ERR_OOM;
@@ -2202,60 +2306,31 @@ ffth_status ffth_server_step(ffth_server* S, int32_t* running, int32_t* waiting)
   if (!S) return FFTH_ERR_INVALID;
   ffth_status st = admit(S);
   if (st != FFTH_OK) return st;
-  // group running jobs by grid, material kind and spectrum precision (the
-  // launches of a group take the first job's kernels); every group's round is
-  // queued on its grid's stream, then the step waits for all streams once
-  // The inner iterations of grids in the multi-size set that share a stream
-  // are deferred and then run for those sizes together, one launch per pass
-  // (issue_merged).
-  GroupMap groups;
-  for (Request* r : S->running)
-    groups[std::make_tuple(r->n[0], r->n[1], r->n[2], r->iso, r->job.P->h16)].push_back(&r->job);
-  S->stage.cursor = 0;
-  std::vector<int> kin(groups.size(), 0);
-  std::vector<InnerSet> inner(groups.size());
-  // A group's inner iterations join a multi-size launch only when another
-  // group with inner iterations this step shares its stream, material kind
-  // and spectrum precision (a launch across grid sizes saves launches there;
-  // a grid alone on its stream keeps the per-size kernels, whose default
-  // tiles compute the same values).
-  const bool merge = S->opts.scheme == FFTH_CG;
-  std::map<std::tuple<hipStream_t, bool, bool>, int> sharing;
-  std::vector<bool> eligible(groups.size(), false);
-  size_t gi = 0;
-  for (auto& kv : groups) {
-    const ffth_plan* P0 = kv.second[0]->P;
-    bool in = false;
-    for (const Job* J : kv.second) in = in || J->phase == PH_INNER;
-    eligible[gi] = merge && in && multi_grid(P0->n);
-    if (eligible[gi]) ++sharing[std::make_tuple(P0->stream, P0->iso, P0->h16)];
-    ++gi;
+  // idle streams with running requests start a round
+  for (size_t k = 0; k < S->streams.size(); ++k)
+    if (!S->rounds[k].busy && (st = issue_round(S, k)) != FFTH_OK) return st;
+  // every round that has finished is completed and its stream goes on; if
+  // none has, the oldest is waited for
+  bool done_any = false;
+  for (size_t k = 0; k < S->streams.size(); ++k) {
+    if (!S->rounds[k].busy) continue;
+    const hipError_t q = hipEventQuery(S->rounds[k].done);
+    if (q == hipErrorNotReady) continue;
+    HIPCHK(q);
+    if ((st = complete_round(S, k)) != FFTH_OK || (st = admit(S)) != FFTH_OK || (st = issue_round(S, k)) != FFTH_OK)
+      return st;
+    done_any = true;
   }
-  gi = 0;
-  for (auto& kv : groups) {
-    const ffth_plan* P0 = kv.second[0]->P;
-    const bool defer = eligible[gi] && sharing[std::make_tuple(P0->stream, P0->iso, P0->h16)] >= 2;
-    if ((st = group_issue(kv.second, S->stage, &kin[gi], defer ? &inner[gi] : nullptr)) != FFTH_OK) return st;
-    ++gi;
-  }
-  if (merge && (st = issue_merged(S, groups, inner, kin)) != FFTH_OK) return st;
-  for (hipStream_t sm : S->streams) HIPCHK(hipStreamSynchronize(sm));
-  gi = 0;
-  for (auto& kv : groups)
-    if ((st = group_advance(kv.second, kin[gi++])) != FFTH_OK) return st;
-  // completed solves: volume averages, results, memory back to the arena
-  std::vector<Request*> still;
-  for (Request* r : S->running) {
-    if (r->job.phase != PH_DONE) {
-      still.push_back(r);
-      continue;
+  if (!done_any) {
+    size_t k = S->streams.size();
+    for (size_t i = 0; i < S->streams.size(); ++i)
+      if (S->rounds[i].busy && (k == S->streams.size() || S->rounds[i].seq < S->rounds[k].seq)) k = i;
+    if (k < S->streams.size()) {
+      HIPCHK(hipEventSynchronize(S->rounds[k].done));
+      if ((st = complete_round(S, k)) != FFTH_OK || (st = admit(S)) != FFTH_OK || (st = issue_round(S, k)) != FFTH_OK)
+        return st;
     }
-    r->res.assign(r->nl, ffth_result{});
-    ffth_status fs = solve_finish(r->P, r->nl, r->eps, r->res.data(), r->t_submit, nullptr);
-    finish_request(S, r, fs);
   }
-  S->running.swap(still);
-  if ((st = admit(S)) != FFTH_OK) return st;
   if (running) *running = (int32_t)S->running.size();
   if (waiting) *waiting = (int32_t)S->waiting.size();
   return FFTH_OK;
@@ -2287,6 +2362,15 @@ ffth_status ffth_cancel(ffth_server* S, uint64_t id) {
   auto it = S->reqs.find(id);
   if (it == S->reqs.end()) return FFTH_ERR_INVALID;
   Request* r = it->second;
+  if (r->state == 1) {
+    // a running request may be in its stream's round: that round completes first
+    const size_t k = stream_index(S, r->P->stream);
+    if (S->rounds[k].busy) {
+      HIPCHK(hipEventSynchronize(S->rounds[k].done));
+      ffth_status st = complete_round(S, k);
+      if (st != FFTH_OK) return st;
+    }
+  }
   if (r->state >= 2) return FFTH_OK;
   if (r->state == 0) {
     S->waiting.erase(std::find(S->waiting.begin(), S->waiting.end(), r));
@@ -2299,14 +2383,15 @@ ffth_status ffth_cancel(ffth_server* S, uint64_t id) {
 
 ffth_status ffth_server_destroy(ffth_server* S) {
   if (!S) return FFTH_ERR_INVALID;
+  for (hipStream_t sm : S->streams) (void)hipStreamSynchronize(sm);   // rounds still in flight
   for (auto& kv : S->reqs) {
     Request* r = kv.second;
     if (r->P) (void)ffth_plan_destroy(r->P);
     delete r;
   }
-  for (hipStream_t sm : S->streams) (void)hipStreamSynchronize(sm);
   for (size_t j = 1; j < S->streams.size(); ++j) (void)hipStreamDestroy(S->streams[j]);
-  (void)hipHostFree(S->stage.h);
+  for (auto& st : S->stages) (void)hipHostFree(st.h);
+  for (auto& rd : S->rounds) (void)hipEventDestroy(rd.done);
   delete S;
   return FFTH_OK;
 }

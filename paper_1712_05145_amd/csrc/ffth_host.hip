@@ -202,6 +202,41 @@ double stiffness_contrast(int nph, bool iso, const double* lame, const double* v
 
 void ffth::set_last_error(const char* msg) { g_last_error = msg ? msg : ""; }
 
+// Pinned host buffers that are handed out again instead of freed: freeing
+// pinned memory synchronizes the whole device, which in a server would stall
+// every stream each time a request finishes.  Sizes are rounded up to powers
+// of two (at least 4 KiB); a plan created with a pool returns its buffers to
+// it when destroyed, and the pool frees them all when released.
+struct HostPool {
+  std::map<size_t, std::vector<void*>> free_;
+  std::vector<void*> all;
+  static size_t rounded(size_t b) {
+    size_t r = 4096;
+    while (r < b) r <<= 1;
+    return r;
+  }
+  void* get(size_t bytes) {
+    std::vector<void*>& v = free_[rounded(bytes)];
+    if (!v.empty()) {
+      void* q = v.back();
+      v.pop_back();
+      return q;
+    }
+    void* q = nullptr;
+    if (hipHostMalloc(&q, rounded(bytes), hipHostMallocDefault) != hipSuccess) return nullptr;
+    all.push_back(q);
+    return q;
+  }
+  void put(void* q, size_t bytes) {
+    if (q) free_[rounded(bytes)].push_back(q);
+  }
+  void release() {
+    for (void* q : all) (void)hipHostFree(q);
+    all.clear();
+    free_.clear();
+  }
+};
+
 struct ffth_plan {
   int n[3];
   long nvox;
@@ -227,6 +262,7 @@ struct ffth_plan {
   SolverState* h_state;   // pinned host mirror (read-back)
   Desc* d_cdesc;          // 4 regions of nloads compacted descriptors
   Desc* h_cdesc;          // pinned staging for them
+  HostPool* hpool = nullptr;   // where h_state and h_cdesc come from (null: hipHostMalloc / hipHostFree)
   int nx64, nx32;         // forward x-pass blocks per precision
   int ni64, ni32;         // inverse x-pass blocks per precision
   int var[4][2] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};   // tile variant per pass (xf, y, z, xi) and FP32/FP64
@@ -1310,6 +1346,32 @@ double now_s() { return std::chrono::duration<double>(std::chrono::steady_clock:
 // ===========================================================================
 // C-ABI
 // ===========================================================================
+namespace {
+
+void* host_get(ffth_plan* P, size_t bytes) {
+  if (P->hpool) return P->hpool->get(bytes);
+  void* q = nullptr;
+  return hipHostMalloc(&q, bytes, hipHostMallocDefault) == hipSuccess ? q : nullptr;
+}
+
+void host_put(ffth_plan* P, void* q, size_t bytes) {
+  if (!q) return;
+  if (P->hpool) P->hpool->put(q, bytes);
+  else (void)hipHostFree(q);
+}
+
+void free_host_bufs(ffth_plan* P) {
+  host_put(P, P->h_state, P->L.nstate * sizeof(SolverState));
+  host_put(P, P->h_cdesc, 4 * (size_t)P->nloads * sizeof(Desc));
+  P->h_state = nullptr;
+  P->h_cdesc = nullptr;
+}
+
+ffth_status plan_create(ffth_plan** out, const ffth_problem* p, const ffth_opts* o, int32_t nloads, int32_t order,
+                        void* workspace, size_t bytes, void* hip_stream, HostPool* pool);
+
+}  // namespace
+
 extern "C" {
 
 void ffth_default_opts(ffth_opts* o) {
@@ -1355,8 +1417,12 @@ const char* ffth_status_string(ffth_status s) {
 
 const char* ffth_last_error(void) { return g_last_error.c_str(); }
 
-ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_opts* o, int32_t nloads, int32_t order,
-                             void* workspace, size_t bytes, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+ffth_status plan_create(ffth_plan** out, const ffth_problem* p, const ffth_opts* o, int32_t nloads, int32_t order,
+                        void* workspace, size_t bytes, void* hip_stream, HostPool* pool) {
   g_last_error.clear();
   if (!out || !p || !o || !workspace) {
     g_last_error = "null argument";
@@ -1421,14 +1487,12 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
   P->d_cdesc = (Desc*)(P->ws + L.cdesc);
   set_blocks(P);
   P->h_desc.assign(L.ndesc, Desc{});
-  if (!hip_ok(hipHostMalloc((void**)&P->h_state, L.nstate * sizeof(SolverState), hipHostMallocDefault),
-              "hipHostMalloc")) {
-    delete P;
-    return FFTH_ERR_DEVICE;
-  }
-  if (!hip_ok(hipHostMalloc((void**)&P->h_cdesc, 4 * (size_t)nloads * sizeof(Desc), hipHostMallocDefault),
-              "hipHostMalloc")) {
-    (void)hipHostFree(P->h_state);
+  P->hpool = pool;
+  P->h_state = (SolverState*)host_get(P, L.nstate * sizeof(SolverState));
+  P->h_cdesc = (Desc*)host_get(P, 4 * (size_t)nloads * sizeof(Desc));
+  if (!P->h_state || !P->h_cdesc) {
+    g_last_error = "hipHostMalloc failed";
+    free_host_bufs(P);
     delete P;
     return FFTH_ERR_DEVICE;
   }
@@ -1490,22 +1554,19 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
   ok = ok && hip_ok(hipMemcpyAsync(&hmax, dmax, sizeof(int), hipMemcpyDeviceToHost, P->stream), "copy") &&
        hip_ok(hipStreamSynchronize(P->stream), "sync");
   if (!ok) {
-    (void)hipHostFree(P->h_state);
-    (void)hipHostFree(P->h_cdesc);
+    free_host_bufs(P);
     delete P;
     return FFTH_ERR_DEVICE;
   }
   if (hmax >= p->nphases) {
     g_last_error = "phase id " + std::to_string(hmax) + " >= nphases";
-    (void)hipHostFree(P->h_state);
-    (void)hipHostFree(P->h_cdesc);
+    free_host_bufs(P);
     delete P;
     return FFTH_ERR_INVALID;
   }
   ffth_status ts = autotune(P);
   if (ts != FFTH_OK) {
-    (void)hipHostFree(P->h_state);
-    (void)hipHostFree(P->h_cdesc);
+    free_host_bufs(P);
     delete P;
     return ts;
   }
@@ -1513,13 +1574,21 @@ ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_
   return FFTH_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+ffth_status ffth_plan_create(ffth_plan** out, const ffth_problem* p, const ffth_opts* o, int32_t nloads, int32_t order,
+                             void* workspace, size_t bytes, void* hip_stream) {
+  return plan_create(out, p, o, nloads, order, workspace, bytes, hip_stream, nullptr);
+}
+
 ffth_status ffth_plan_destroy(ffth_plan* P) {
   if (!P) return FFTH_ERR_INVALID;
   (void)hipStreamSynchronize(P->stream);
   prof_flush(P);
   for (hipEvent_t e : P->pool) (void)hipEventDestroy(e);
-  (void)hipHostFree(P->h_cdesc);
-  (void)hipHostFree(P->h_state);
+  free_host_bufs(P);
   delete P;
   return FFTH_OK;
 }
@@ -1902,6 +1971,12 @@ struct ffth_server {
   size_t bytes = 0;
   hipStream_t stream = nullptr;
   std::vector<hipStream_t> streams;         // [0] = the caller's; the rest created here
+  // Admission (material upload, phase-id check, descriptors, states) runs on
+  // a stream of its own, which no round uses, so that its synchronizations
+  // wait for the admission's own copies only and never for a round in flight
+  // on the request's stream; the request's plan then moves to that stream.
+  hipStream_t admit_stream = nullptr;
+  HostPool hpool;                           // pinned mirrors of the request plans
   std::map<std::array<int, 3>, int> size_stream;   // grid -> index into streams
   ffth_opts opts{};
   int max_running = 0;
@@ -1982,8 +2057,8 @@ ffth_status admit(ffth_server* S) {
     // request is what the plan path computes with autotuning off
     ffth_opts po = S->opts;
     if (po.scheme == FFTH_CG && multi_grid(r->n)) po.autotune = 0;
-    ffth_status st = ffth_plan_create(&r->P, &r->prob, &po, r->nl, 0, S->arena + off, r->ws_bytes,
-                                      stream_for(S, r->n));
+    ffth_status st = plan_create(&r->P, &r->prob, &po, r->nl, 0, S->arena + off, r->ws_bytes, S->admit_stream,
+                                 &S->hpool);
     if (st != FFTH_OK) {
       r->P = nullptr;
       finish_request(S, r, st);
@@ -1992,10 +2067,13 @@ ffth_status admit(ffth_server* S) {
     r->eps = (double*)(S->arena + off + al(r->ws_bytes));
     r->t_start = now_s();
     build_solve_descs(r->P, r->nl, r->E.data(), r->eps, false);
-    if ((st = upload_descs(r->P)) != FFTH_OK || (st = solve_begin(r->P, r->nl, false)) != FFTH_OK) {
+    if ((st = upload_descs(r->P)) != FFTH_OK || (st = solve_begin(r->P, r->nl, false)) != FFTH_OK ||
+        (st = hip_ok(hipStreamSynchronize(S->admit_stream), "sync") ? FFTH_OK : FFTH_ERR_DEVICE) != FFTH_OK) {
       finish_request(S, r, st);
       continue;
     }
+    // everything the admission queued has completed: the rounds take over
+    r->P->stream = stream_for(S, r->n);
     r->job = Job();
     r->job.P = r->P;
     r->job.nl = r->nl;
@@ -2248,7 +2326,9 @@ ffth_status ffth_server_create(ffth_server** out, void* arena, size_t arena_byte
     ok = hip_ok(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreate");
     if (ok) S->streams.push_back(st);
   }
+  ok = ok && hip_ok(hipStreamCreateWithFlags(&S->admit_stream, hipStreamNonBlocking), "hipStreamCreate");
   if (!ok) {
+    if (S->admit_stream) (void)hipStreamDestroy(S->admit_stream);
     for (size_t j = 1; j < S->streams.size(); ++j) (void)hipStreamDestroy(S->streams[j]);
     for (auto& st : S->stages)
       if (st.h) (void)hipHostFree(st.h);
@@ -2389,6 +2469,8 @@ ffth_status ffth_server_destroy(ffth_server* S) {
     if (r->P) (void)ffth_plan_destroy(r->P);
     delete r;
   }
+  S->hpool.release();
+  (void)hipStreamDestroy(S->admit_stream);
   for (size_t j = 1; j < S->streams.size(); ++j) (void)hipStreamDestroy(S->streams[j]);
   for (auto& st : S->stages) (void)hipHostFree(st.h);
   for (auto& rd : S->rounds) (void)hipEventDestroy(rd.done);

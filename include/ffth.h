@@ -309,8 +309,9 @@ ffth_status ffth_submit(ffth_server *srv, const ffth_problem *p, int32_t nloads,
  * admits what fits, starts a round on every idle stream that has running
  * requests, and completes every round that has finished (phase transitions,
  * finished requests, whose memory goes back to the arena) and starts that
- * stream's next one; if no round has finished it waits for the oldest.  So
- * small grids are not held to the pace of large ones.  running / waiting (may
+ * stream's next one; if no round has finished it polls the rounds' events
+ * until one has (the calling thread spins, yielding between polls).  So small
+ * grids are not held to the pace of large ones.  running / waiting (may
  * be NULL) receive the queue sizes after it. */
 ffth_status ffth_server_step(ffth_server *srv, int32_t *running, int32_t *waiting);
 /* FFTH_ERR_BUSY until complete; then the request's status, res[nloads] filled,

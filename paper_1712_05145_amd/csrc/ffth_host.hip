@@ -18,6 +18,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "admission.h"
@@ -1988,7 +1989,6 @@ struct ffth_server {
   // passed, independently of the other streams.
   struct Round {
     bool busy = false;
-    uint64_t seq = 0;                      // issue order (the oldest busy round is waited for first)
     hipEvent_t done = nullptr;             // recorded after the round's last command
     std::vector<std::vector<Job*>> groups; // the round's launch groups
     std::vector<int> kin;                  // inner iterations each group ran
@@ -1996,7 +1996,6 @@ struct ffth_server {
   std::vector<Round> rounds;               // per stream
   std::vector<Stage> stages;               // descriptor staging per stream (a round's are in flight)
   size_t stage_bytes = 0;                  // arena bytes of all streams' staging areas
-  uint64_t seq = 0;
   FreeList free_;                          // free ranges of the arena
   std::deque<Request*> waiting;
   std::vector<Request*> running;
@@ -2230,7 +2229,6 @@ ffth_status issue_round(ffth_server* S, size_t k) {
   if (merge && (st = issue_merged(S, stage, groups, inner, kin)) != FFTH_OK) return st;
   HIPCHK(hipEventRecord(R.done, sm));
   R.busy = true;
-  R.seq = ++S->seq;
   R.groups.clear();
   for (auto& kv : groups) R.groups.push_back(kv.second);
   R.kin = kin;
@@ -2390,26 +2388,22 @@ ffth_status ffth_server_step(ffth_server* S, int32_t* running, int32_t* waiting)
   for (size_t k = 0; k < S->streams.size(); ++k)
     if (!S->rounds[k].busy && (st = issue_round(S, k)) != FFTH_OK) return st;
   // every round that has finished is completed and its stream goes on; if
-  // none has, the oldest is waited for
-  bool done_any = false;
-  for (size_t k = 0; k < S->streams.size(); ++k) {
-    if (!S->rounds[k].busy) continue;
-    const hipError_t q = hipEventQuery(S->rounds[k].done);
-    if (q == hipErrorNotReady) continue;
-    HIPCHK(q);
-    if ((st = complete_round(S, k)) != FFTH_OK || (st = admit(S)) != FFTH_OK || (st = issue_round(S, k)) != FFTH_OK)
-      return st;
-    done_any = true;
-  }
-  if (!done_any) {
-    size_t k = S->streams.size();
-    for (size_t i = 0; i < S->streams.size(); ++i)
-      if (S->rounds[i].busy && (k == S->streams.size() || S->rounds[i].seq < S->rounds[k].seq)) k = i;
-    if (k < S->streams.size()) {
-      HIPCHK(hipEventSynchronize(S->rounds[k].done));
+  // none has, the events are polled until one has, so that whichever stream
+  // finishes first is the first to go on
+  for (bool done_any = false; !done_any;) {
+    bool busy = false;
+    for (size_t k = 0; k < S->streams.size(); ++k) {
+      if (!S->rounds[k].busy) continue;
+      busy = true;
+      const hipError_t q = hipEventQuery(S->rounds[k].done);
+      if (q == hipErrorNotReady) continue;
+      HIPCHK(q);
       if ((st = complete_round(S, k)) != FFTH_OK || (st = admit(S)) != FFTH_OK || (st = issue_round(S, k)) != FFTH_OK)
         return st;
+      done_any = true;
     }
+    if (!busy) break;
+    if (!done_any) std::this_thread::yield();
   }
   if (running) *running = (int32_t)S->running.size();
   if (waiting) *waiting = (int32_t)S->waiting.size();

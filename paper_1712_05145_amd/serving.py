@@ -1,6 +1,7 @@
 """Serving driver over the libffth request server (ffth_server_* in
-include/ffth.h): a caller-owned HBM arena, arrival-order admission by
-memory, continuous batching of running solves, and a wall-clock replay of a
+include/ffth.h): a caller-owned HBM arena, admission by memory (least work
+first, with a bound on how often a request may be passed over), continuous
+batching of running solves on per-grid streams, and a wall-clock replay of a
 Poisson request stream reporting p50/p99 latency beside throughput.
 
 All solving happens in libffth; this module allocates the arena and the

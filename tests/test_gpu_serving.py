@@ -215,3 +215,44 @@ def test_multi_size_binary16_and_anisotropic_match_oracle():
         cg = np.array([r["mean_stress"] for r in res]).T
         d = np.sqrt(np.outer(np.diag(c[5]), np.diag(c[5])))
         assert np.all(np.abs(cg - c[5]) <= 1e-7 * d), np.abs(cg - c[5]).max()
+
+
+def _ms(res):
+    return np.array([r["mean_stress"] for r in res])
+
+
+def test_cancel_running_and_close_with_rounds_in_flight():
+    """Three grids on three streams, their rounds in flight: cancelling a
+    running request completes its stream's round first and frees its memory;
+    the other two finish bit-identical to their runs alone, and so does the
+    cancelled request submitted again into the freed memory.  A server
+    closed with rounds in flight drains them first, and a new server then
+    computes the same results."""
+    torch = require_gpu()
+    from paper_1712_05145_amd.serving import Server
+    reqs = {"a": _req(64, 0.25, 20.0, 41), "b": _req(32, 0.3, 30.0, 42), "c": _req(48, 0.2, 10.0, 43)}
+    alone = {k: _alone(r) for k, r in reqs.items()}
+    assert all(alone[k][0] == 0 for k in reqs)
+    srv = Server(8 << 30, max_running=8)
+    ids = {k: srv.submit(*r, np.eye(6)) for k, r in reqs.items()}
+    running, waiting = srv.step()
+    assert running == 3 and waiting == 0
+    srv.step()
+    srv.cancel(ids["a"])          # a 64^3 solve is still running after two steps
+    st, _ = srv.poll(ids["a"])
+    assert st == ffth.FFTH_ERR_CANCELLED
+    done = _drain(srv, [ids["b"], ids["c"]])
+    for k in ("b", "c"):
+        st, res = done[ids[k]]
+        assert st == 0, k
+        assert np.array_equal(_ms(res), _ms(alone[k][1])), k
+    rid = srv.submit(*reqs["a"], np.eye(6))
+    st, res = _drain(srv, [rid])[rid]
+    assert st == 0 and np.array_equal(_ms(res), _ms(alone["a"][1]))
+    for r in reqs.values():
+        srv.submit(*r, np.eye(6))
+    srv.step()
+    srv.step()
+    srv.close()
+    st, res = _alone(reqs["b"])
+    assert st == 0 and np.array_equal(_ms(res), _ms(alone["b"][1]))

@@ -930,14 +930,19 @@ struct Stage {
   Desc* h;
   int cap;
   int cursor;
+  bool overflow = false;   // an append found the area full (the round is refused)
 };
 
 // Append the descriptors of role r of job J whose state (slot base + l) was
 // active at the last read-back.
 int stage_append(Stage& st, const Job& J, Role r, int base) {
   int k = 0;
-  for (int l = 0; l < J.nl && st.cursor < st.cap; ++l)
+  for (int l = 0; l < J.nl; ++l)
     if (J.P->h_state[base + l].active) {
+      if (st.cursor >= st.cap) {
+        st.overflow = true;
+        break;
+      }
       st.h[st.cursor++] = J.P->h_desc[desc_slot(J.P, r, l)];
       ++k;
     }
@@ -1019,6 +1024,11 @@ ffth_status group_issue(std::vector<Job*>& jobs, Stage& st, int* kin_out, InnerS
       kin = std::min(kin, std::max(1, o.max_iter - J->inner_total));
     }
   }
+  if (st.overflow) {
+    st.overflow = false;
+    g_last_error = "descriptor staging area too small for the round";
+    return FFTH_ERR_INVALID;
+  }
   // binary16 kernels read the operator output through spec2: every inner
   // descriptor must match the launch's spectrum precision
   if (!h16_launch_ok(st.h + from[3], cnt[3], dims->h16)) {
@@ -1033,8 +1043,12 @@ ffth_status group_issue(std::vector<Job*>& jobs, Stage& st, int* kin_out, InnerS
   if (o.scheme == FFTH_CG) {
     for (Job* J : jobs) {
       if (J->phase != PH_A) continue;
-      for (int l = 0; l < J->nl && st.cursor < st.cap; ++l)
+      for (int l = 0; l < J->nl; ++l)
         if (J->P->h_state[J->nl + l].xpend) {
+          if (st.cursor >= st.cap) {
+            g_last_error = "descriptor staging area too small for the round";
+            return FFTH_ERR_INVALID;
+          }
           st.h[st.cursor++] = J->P->h_desc[desc_slot(J->P, R_INNER, l)];
           ++cntF;
         }
